@@ -1,0 +1,191 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+import this module.  It marshals numpy arrays into the C oracle and adds no
+arithmetic of its own.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmhd_oracle.so")
+_lib = None
+
+BC_PERIODIC, BC_REFLECT = 0, 1
+EOS_IDEAL, EOS_GASRAD = 0, 1
+XI_LINEAR, XI_STEP, XI_OFF = 0, 1, 2
+
+_DP = C.POINTER(C.c_double)
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+        ("bcz", C.c_int), ("eos", C.c_int),
+        ("gamma", C.c_double), ("mu", C.c_double), ("rgas", C.c_double),
+        ("arad", C.c_double), ("gz", C.c_double),
+        ("rk_order", C.c_int), ("newton_tol", C.c_double),
+        ("newton_maxit", C.c_int), ("mach_cut", C.c_double),
+        ("xi_mode", C.c_int),
+        ("bg_cc", _DP), ("bg_fz", _DP), ("heat", _DP), ("force", _DP),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # noqa: F401  (package import)
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        L = _lib
+        L.orc_step.argtypes = [C.POINTER(_Cfg), _DP, _DP, _DP, _DP, _DP, C.c_double]
+        L.orc_residual.argtypes = [C.POINTER(_Cfg)] + [_DP] * 10
+        L.orc_compute_dt.argtypes = [C.POINTER(_Cfg), _DP, _DP, _DP, _DP, _DP,
+                                     C.c_double, _DP]
+        L.orc_divb.argtypes = [C.POINTER(_Cfg), _DP, _DP, _DP, _DP]
+        L.orc_divb.restype = None
+        L.orc_primitives.argtypes = [C.POINTER(_Cfg)] + [_DP] * 7
+        L.orc_riemann.argtypes = [C.POINTER(_Cfg), _DP, _DP, C.c_double, _DP]
+        L.orc_eos_invert.argtypes = [C.POINTER(_Cfg), C.c_double, C.c_double,
+                                     C.c_double, _DP, C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int)]
+        L.orc_eos_thermo.argtypes = [C.POINTER(_Cfg), C.c_double, C.c_double,
+                                     _DP, _DP, _DP, _DP]
+        L.orc_vanleer.argtypes = [C.c_double, C.c_double]
+        L.orc_vanleer.restype = C.c_double
+        L.orc_num_threads.restype = C.c_int
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "need C-contiguous float64"
+    return a.ctypes.data_as(_DP)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+DEFAULTS = dict(
+    bcz=BC_PERIODIC, eos=EOS_IDEAL, gamma=5.0 / 3.0, mu=0.6, rgas=0.0, arad=0.0,
+    gz=0.0, rk_order=2, newton_tol=1e-11, newton_maxit=50, mach_cut=0.6,
+    xi_mode=XI_LINEAR,
+)
+
+
+class Oracle:
+    """The oracle bound to one problem description (a dict of grid and
+    physics parameters, plus optional background, heating and forcing
+    arrays)."""
+
+    def __init__(self, params: dict, bg_cc=None, bg_fz=None, heat=None, force=None):
+        p = dict(DEFAULTS)
+        p.update(params)
+        self.p = p
+        nx, ny, nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+        lo, hi = p.get("lo", (0.0, 0.0, 0.0)), p.get("hi", (1.0, 1.0, 1.0))
+        self.shape = (nz, ny, nx)
+        self.nzf = nz + 1 if p["bcz"] == BC_REFLECT else nz
+        self._keep = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (bg_cc, bg_fz, heat, force)]
+        bcc, bfz, ht, fc = self._keep
+        self.cfg = _Cfg(
+            nx, ny, nz,
+            (hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny, (hi[2] - lo[2]) / nz,
+            int(p["bcz"]), int(p["eos"]), float(p["gamma"]), float(p["mu"]),
+            float(p["rgas"]), float(p["arad"]), float(p["gz"]), int(p["rk_order"]),
+            float(p["newton_tol"]), int(p["newton_maxit"]), float(p["mach_cut"]),
+            int(p["xi_mode"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
+        )
+
+    # -- state helpers -------------------------------------------------
+    def _state(self, st):
+        U = st["U"]
+        for k in ("U", "Bx", "By", "Bz"):
+            assert st[k].dtype == np.float64 and st[k].flags["C_CONTIGUOUS"], k
+        assert U.shape == (5,) + self.shape
+        T = st.get("T")
+        if self.p["eos"] == EOS_GASRAD:
+            assert T is not None and T.shape == self.shape
+        return U, st["Bx"], st["By"], st["Bz"], T
+
+    def step(self, st: dict, dt: float) -> None:
+        U, Bx, By, Bz, T = self._state(st)
+        _check(lib().orc_step(C.byref(self.cfg), _ptr(U), _ptr(Bx), _ptr(By), _ptr(Bz),
+                              _ptr(T), float(dt)), "orc_step")
+
+    def residual(self, st: dict):
+        U, Bx, By, Bz, T = self._state(st)
+        RU = np.empty_like(U)
+        RBx, RBy, RBz = np.empty_like(Bx), np.empty_like(By), np.empty_like(Bz)
+        Tout = None if T is None else np.empty_like(T)
+        _check(lib().orc_residual(C.byref(self.cfg), _ptr(U), _ptr(Bx), _ptr(By), _ptr(Bz),
+                                  _ptr(T), _ptr(Tout), _ptr(RU), _ptr(RBx), _ptr(RBy),
+                                  _ptr(RBz)), "orc_residual")
+        return RU, RBx, RBy, RBz, Tout
+
+    def compute_dt(self, st: dict, cfl: float) -> float:
+        U, Bx, By, Bz, T = self._state(st)
+        out = C.c_double(0.0)
+        _check(lib().orc_compute_dt(C.byref(self.cfg), _ptr(U), _ptr(Bx), _ptr(By),
+                                    _ptr(Bz), _ptr(T), float(cfl), C.byref(out)),
+               "orc_compute_dt")
+        return out.value
+
+    def divb(self, st: dict):
+        out = np.empty(self.shape)
+        lib().orc_divb(C.byref(self.cfg), _ptr(st["Bx"]), _ptr(st["By"]), _ptr(st["Bz"]),
+                       _ptr(out))
+        return out
+
+    def primitives(self, st: dict):
+        U, Bx, By, Bz, T = self._state(st)
+        out = np.empty((10,) + self.shape)
+        Tout = None if T is None else np.empty_like(T)
+        _check(lib().orc_primitives(C.byref(self.cfg), _ptr(U), _ptr(Bx), _ptr(By),
+                                    _ptr(Bz), _ptr(T), _ptr(Tout), _ptr(out)),
+               "orc_primitives")
+        return out, Tout
+
+    # -- pointwise routines -------------------------------------------
+    def riemann(self, WL, WR, bn):
+        WL = np.ascontiguousarray(WL, dtype=np.float64)
+        WR = np.ascontiguousarray(WR, dtype=np.float64)
+        F = np.empty(7)
+        _check(lib().orc_riemann(C.byref(self.cfg), _ptr(WL), _ptr(WR), float(bn), _ptr(F)),
+               "orc_riemann")
+        return F
+
+    def eos_invert(self, rho, eint, tguess):
+        T = C.c_double(0.0)
+        it, fb = C.c_int(0), C.c_int(0)
+        _check(lib().orc_eos_invert(C.byref(self.cfg), float(rho), float(eint), float(tguess),
+                                    C.byref(T), C.byref(it), C.byref(fb)), "orc_eos_invert")
+        return T.value, it.value, fb.value
+
+    def eos_thermo(self, rho, T):
+        P, e, cv, cs2 = (C.c_double(0.0) for _ in range(4))
+        lib().orc_eos_thermo(C.byref(self.cfg), float(rho), float(T), C.byref(P), C.byref(e),
+                             C.byref(cv), C.byref(cs2))
+        return P.value, e.value, cv.value, cs2.value
+
+
+def vanleer(a: float, b: float) -> float:
+    return lib().orc_vanleer(float(a), float(b))
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
