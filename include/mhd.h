@@ -1,0 +1,178 @@
+/*
+ * mhd.h -- C ABI of the MI355X (gfx950) explicit finite-volume MHD step.
+ *
+ * The library advances the ideal-MHD system with gravity and energy /
+ * momentum sources (arXiv 2604.12672, Sect. 2.1) by one explicit SSP-RK
+ * step (Sect. 2.9) of the well-balanced (Sect. 2.8), van Leer reconstructed
+ * (Sect. 2.5), LHLLD (Sect. 2.6), Contact-CT (Sect. 2.4) scheme, with a
+ * per-cell Newton inversion T(rho, e_int) for the gas+radiation EOS
+ * (Sect. 2.2, eqs. prad/erad).  One fused HIP kernel computes each RK stage;
+ * a reduction kernel computes the CFL step (eq. cfl).
+ *
+ * Grid and storage.  Uniform Cartesian grid of nx*ny*nz cells on the box
+ * [lo, hi]; x and y are periodic; z is periodic or reflecting.  All state
+ * arrays are FP64, structure-of-arrays, x fastest, interior cells only:
+ *   U   [5][nz][ny][nx]  rho, m_x, m_y, m_z, E   (E includes |B_cc|^2 / 2,
+ *                        B_cc = mean of the two faces on each axis)
+ *   Bx  [nz][ny][nx]     Bx[k][j][i] = B_x on the face x_{i-1/2}
+ *   By  [nz][ny][nx]     By[k][j][i] = B_y on the face y_{j-1/2}
+ *   Bz  [nzf][ny][nx]    Bz[k][j][i] = B_z on the face z_{k-1/2};
+ *                        nzf = nz (periodic z) or nz+1 (reflecting z; the
+ *                        wall planes k = 0 and k = nz hold zero)
+ *   T   [nz][ny][nx]     temperature (gas+radiation EOS only)
+ *
+ * Ownership.  The caller owns every pointer it passes; the library copies
+ * in and out on its stream and never keeps caller pointers.  The library
+ * owns its device buffers (allocated in mhd_init_grid, freed in
+ * mhd_destroy).  `where` says whether a pointer is host memory
+ * (MHD_HOST) or device memory (MHD_DEVICE, e.g. a torch CUDA tensor).
+ *
+ * Errors.  Every call returns 0 (MHD_OK) or a negative MHD_ERR_* code and
+ * records a message for mhd_last_error.  No exception crosses the ABI.
+ * mhd_step / mhd_advance are asynchronous on the context stream; a
+ * non-physical state met on the device (rho <= 0, e_int <= 0, EOS failure)
+ * is latched in a device flag and returned by the next synchronising call
+ * (mhd_compute_dt, mhd_get_state, mhd_diagnostics, mhd_sync).  Calls in the
+ * wrong order (e.g. a step before mhd_set_state) return MHD_ERR_STATE.
+ * A context is not thread-safe; calls on one context are serialised by the
+ * caller.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHD_OK 0
+#define MHD_ERR_ARG (-1)        /* invalid argument or unsupported option    */
+#define MHD_ERR_NO_DEVICE (-2)  /* no gfx950 device / no HIP runtime         */
+#define MHD_ERR_HIP (-3)        /* a HIP runtime call failed                 */
+#define MHD_ERR_UNPHYSICAL (-4) /* rho <= 0, e_int <= 0 or non-finite state  */
+#define MHD_ERR_EOS (-5)        /* temperature inversion did not converge    */
+#define MHD_ERR_STATE (-6)      /* call out of order                         */
+
+#define MHD_BC_PERIODIC 0
+#define MHD_BC_REFLECT 1
+
+#define MHD_EOS_IDEAL 0   /* P = (gamma-1) rho e_int                          */
+#define MHD_EOS_GASRAD 1  /* P = rho R T/mu + a T^4/3 (eqs. prad, erad)       */
+
+#define MHD_PREC_FP64 0   /* every operation in FP64                          */
+#define MHD_PREC_SPLIT 1  /* reconstruction, Riemann flux and EMFs in FP32 on
+                             deviations from the background; background, RK
+                             accumulation, flux divergence, curl and EOS
+                             Newton polish in FP64                             */
+
+#define MHD_GUESS_PREV_T 0 /* Newton starts from the previous solution (Sect. 2.2) */
+#define MHD_GUESS_MLP 1    /* Newton starts from the learned guess (mhd_set_eos_mlp) */
+
+#define MHD_XI_LINEAR 0   /* xi = min(1, max(M_L, M_R) / mach_cut)          */
+#define MHD_XI_STEP 1     /* xi = max(M_L, M_R) if below mach_cut, else 1   */
+#define MHD_XI_OFF 2      /* xi = 1 (plain HLLD)                            */
+
+#define MHD_HOST 0
+#define MHD_DEVICE 1
+
+typedef struct mhd_ctx mhd_ctx; /* opaque */
+
+typedef struct {
+  int32_t nx, ny, nz;     /* interior cells, each >= 1                         */
+  double lo[3], hi[3];    /* box corners, hi > lo                              */
+  int32_t bc[3];          /* bc[0] = bc[1] = MHD_BC_PERIODIC;
+                             bc[2] = MHD_BC_PERIODIC or MHD_BC_REFLECT        */
+  int32_t eos;            /* MHD_EOS_*                                         */
+  double gamma;           /* adiabatic index of the gas (> 1)                  */
+  double mu, rgas, arad;  /* gas+radiation constants in code units            */
+  double grav[3];         /* constant gravity; only grav[2] may be nonzero     */
+  int32_t rk_order;       /* 2 (SSP-RK2) or 3 (SSP-RK3)                        */
+  int32_t precision;      /* MHD_PREC_*                                        */
+  int32_t eos_guess;      /* MHD_GUESS_*                                       */
+  double newton_tol;      /* relative residual |de|/e_int (paper: 1e-11)       */
+  int32_t newton_maxit;   /* Newton steps before the bracketed solve           */
+  double mach_cut;        /* Mach threshold of the LHLLD factor (paper: 0.6)   */
+  int32_t xi_mode;        /* MHD_XI_*                                          */
+} mhd_grid_desc;
+
+typedef struct {
+  double divb_max;        /* max over cells of |div B| dx_min / max |B_face|   */
+  double divb_l2;         /* sqrt(mean (div B dx_min)^2) / max |B_face|        */
+  double bface_max;       /* max |B_face|                                      */
+  double total[5];        /* sums over cells of rho, m_x, m_y, m_z, E          */
+  double bflux_x0;        /* sum of Bx over the plane x_{-1/2}                 */
+  int64_t newton_iters;   /* Newton steps taken in the last stage              */
+  int64_t newton_max;     /* largest Newton count of one cell, last stage      */
+  int64_t fallbacks;      /* cells that needed the bracketed solve, last stage */
+  int32_t error_flags;    /* latched device flags (bit 0 unphysical, bit 1 EOS) */
+} mhd_diag;
+
+/* Create a context on the current HIP device, launching on `hip_stream`
+   (a hipStream_t; NULL = the null stream).  Validates the descriptor
+   (MHD_ERR_ARG), checks for a gfx950 device (MHD_ERR_NO_DEVICE) and
+   allocates all device buffers (MHD_ERR_HIP).  On error *out is NULL. */
+int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out);
+
+/* Hydrostatic background W_hat known a priori (Sect. 2.8, deviation
+   method): host arrays w_cc [4][nz] at cell-centre heights and w_fz
+   [4][nzf] at z-face heights, rows rho_hat, P_hat, gamma_e_hat,
+   gamma_c_hat.  The background has zero velocity and field.  Without this
+   call the background is zero (the full state is reconstructed). */
+int mhd_set_background(mhd_ctx *ctx, const double *w_cc, const double *w_fz);
+
+/* Energy source per unit volume heat [nz] (host, nullable) and acceleration
+   field force [3][nz][ny][nx] (`where`, nullable; adds rho f to the momentum
+   and m.f to the energy equation).  Neither is part of the equilibrium
+   source S_hat. */
+int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *force,
+                    int32_t where);
+
+/* Load the state.  T (nullable) is the initial temperature guess for
+   MHD_GUESS_PREV_T; when NULL the library solves T with the bracketed
+   method.  The wall planes of Bz are forced to zero for a reflecting z. */
+int mhd_set_state(mhd_ctx *ctx, const double *U, const double *Bx,
+                  const double *By, const double *Bz, const double *T,
+                  int32_t where);
+
+/* CFL step dt = cfl / max_cells sum_s (|v_s| + c_f,s)/dx_s (eq. cfl), axes
+   with one cell left out.  Synchronises the stream; returns latched device
+   errors. */
+int mhd_compute_dt(mhd_ctx *ctx, double cfl, double *dt_out);
+
+/* One SSP-RK step of size dt > 0 (asynchronous). */
+int mhd_step(mhd_ctx *ctx, double dt);
+
+/* nsteps steps, each with dt = cfl / (max signal speed) computed on the
+   device from the state at the start of the step (asynchronous; no host
+   round trip).  Equivalent to nsteps x (mhd_compute_dt; mhd_step). */
+int mhd_advance(mhd_ctx *ctx, double cfl, int32_t nsteps);
+
+/* Copy the state out (synchronises).  T (nullable) receives the current
+   temperature (gas+radiation only). */
+int mhd_get_state(mhd_ctx *ctx, double *U, double *Bx, double *By, double *Bz,
+                  double *T, int32_t where);
+
+/* Wait for queued work; returns latched device errors. */
+int mhd_sync(mhd_ctx *ctx);
+
+/* div B (eq. divb), conservation totals, Newton statistics (synchronises). */
+int mhd_diagnostics(mhd_ctx *ctx, mhd_diag *out);
+
+/* Message of the last failed call on this context ("" if none); a message
+   for a failed mhd_init_grid is returned for ctx == NULL. */
+const char *mhd_last_error(const mhd_ctx *ctx);
+
+/* Free the context and its device buffers (NULL is a no-op). */
+int mhd_destroy(mhd_ctx *ctx);
+
+/* Kernel launch geometry of the stage kernel (for tests and profiling):
+   tile edge in cells and z-segment length in planes. */
+int mhd_launch_info(const mhd_ctx *ctx, int32_t *tile, int32_t *zseg,
+                    int32_t *blocks);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,489 @@
+// mhd_api.hip -- host side of the C ABI declared in include/mhd.h:
+// argument validation, device buffers, stage sequencing and error latching.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mhd_internal.h"
+
+struct mhd_ctx {
+  mhd::Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_init_err;
+
+int fail(mhd_ctx *h, int code, const std::string &msg) {
+  if (h) h->c.err = msg;
+  return code;
+}
+
+int hip_fail(mhd_ctx *h, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, MHD_ERR_HIP, m);
+}
+
+#define HIPCHK(h, call)                                      \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call);   \
+  } while (0)
+
+// SSP-RK stage coefficients (Sect. 2.9): U_new = a U^n + b U^(s) - c dt R(U^(s))
+const double kRK2[2][3] = {{0.0, 1.0, 1.0}, {0.5, 0.5, 0.5}};
+const double kRK3[3][3] = {{0.0, 1.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+
+int check_desc(const mhd_grid_desc *d, std::string &msg) {
+  if (!d) {
+    msg = "descriptor is NULL";
+    return MHD_ERR_ARG;
+  }
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) {
+    msg = "nx, ny, nz must be >= 1";
+    return MHD_ERR_ARG;
+  }
+  const double cells = (double)d->nx * d->ny * d->nz;
+  if (cells > 4.0e9) {
+    msg = "grid too large";
+    return MHD_ERR_ARG;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!(d->hi[a] > d->lo[a]) || !std::isfinite(d->hi[a] - d->lo[a])) {
+      msg = "box must have hi > lo on every axis";
+      return MHD_ERR_ARG;
+    }
+  if (d->bc[0] != MHD_BC_PERIODIC || d->bc[1] != MHD_BC_PERIODIC) {
+    msg = "x and y boundaries must be periodic";
+    return MHD_ERR_ARG;
+  }
+  if (d->bc[2] != MHD_BC_PERIODIC && d->bc[2] != MHD_BC_REFLECT) {
+    msg = "z boundary must be periodic or reflecting";
+    return MHD_ERR_ARG;
+  }
+  if (d->bc[2] == MHD_BC_REFLECT && d->nz < 2) {
+    msg = "reflecting z needs nz >= 2";
+    return MHD_ERR_ARG;
+  }
+  if (d->eos != MHD_EOS_IDEAL && d->eos != MHD_EOS_GASRAD) {
+    msg = "unknown eos";
+    return MHD_ERR_ARG;
+  }
+  if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) {
+    msg = "gamma must be > 1";
+    return MHD_ERR_ARG;
+  }
+  if (d->eos == MHD_EOS_GASRAD) {
+    if (!(d->mu > 0.0) || !(d->rgas > 0.0) || !(d->arad >= 0.0)) {
+      msg = "gas+radiation EOS needs mu > 0, rgas > 0, arad >= 0";
+      return MHD_ERR_ARG;
+    }
+    if (!(d->newton_tol > 0.0) || d->newton_maxit < 0) {
+      msg = "newton_tol must be > 0 and newton_maxit >= 0";
+      return MHD_ERR_ARG;
+    }
+  }
+  if (d->grav[0] != 0.0 || d->grav[1] != 0.0 || !std::isfinite(d->grav[2])) {
+    msg = "only a finite grav[2] may be nonzero";
+    return MHD_ERR_ARG;
+  }
+  if (d->rk_order != 2 && d->rk_order != 3) {
+    msg = "rk_order must be 2 or 3";
+    return MHD_ERR_ARG;
+  }
+  if (d->precision != MHD_PREC_FP64 && d->precision != MHD_PREC_SPLIT) {
+    msg = "unknown precision";
+    return MHD_ERR_ARG;
+  }
+  if (d->eos_guess != MHD_GUESS_PREV_T && d->eos_guess != MHD_GUESS_MLP) {
+    msg = "unknown eos_guess";
+    return MHD_ERR_ARG;
+  }
+  if (d->eos_guess == MHD_GUESS_MLP) {
+    msg = "the learned EOS guess is not available in this build";
+    return MHD_ERR_ARG;
+  }
+  if (d->xi_mode < MHD_XI_LINEAR || d->xi_mode > MHD_XI_OFF) {
+    msg = "unknown xi_mode";
+    return MHD_ERR_ARG;
+  }
+  if (d->xi_mode != MHD_XI_OFF && !(d->mach_cut > 0.0)) {
+    msg = "mach_cut must be > 0";
+    return MHD_ERR_ARG;
+  }
+  return MHD_OK;
+}
+
+hipMemcpyKind kind_in(int32_t where) {
+  return where == MHD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_out(int32_t where) {
+  return where == MHD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+int latched(mhd_ctx *h) {
+  mhd::Ctx &c = h->c;
+  int flags = 0;
+  HIPCHK(h, hipMemcpyAsync(&flags, c.flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  if (flags & 2) return fail(h, MHD_ERR_EOS, "temperature inversion failed on the device");
+  if (flags & 1)
+    return fail(h, MHD_ERR_UNPHYSICAL, "non-physical state on the device (rho <= 0 or e_int <= 0)");
+  return MHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
+  if (!out) return MHD_ERR_ARG;
+  *out = nullptr;
+  std::string msg;
+  int rc = check_desc(desc, msg);
+  if (rc) {
+    g_init_err = msg;
+    return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_init_err = "no HIP device";
+    return MHD_ERR_NO_DEVICE;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_init_err = std::string("device is not gfx950: ") + prop.gcnArchName;
+    return MHD_ERR_NO_DEVICE;
+  }
+  mhd_ctx *h = new (std::nothrow) mhd_ctx();
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  c.d = *desc;
+  c.device = dev;
+  c.stream = (hipStream_t)hip_stream;
+  mhd::Phys &ph = c.ph;
+  ph.nx = desc->nx;
+  ph.ny = desc->ny;
+  ph.nz = desc->nz;
+  ph.reflect = desc->bc[2] == MHD_BC_REFLECT;
+  ph.nzf = ph.reflect ? desc->nz + 1 : desc->nz;
+  ph.gasrad = desc->eos == MHD_EOS_GASRAD;
+  ph.dx = (desc->hi[0] - desc->lo[0]) / desc->nx;
+  ph.dy = (desc->hi[1] - desc->lo[1]) / desc->ny;
+  ph.dz = (desc->hi[2] - desc->lo[2]) / desc->nz;
+  ph.idx = 1.0 / ph.dx;
+  ph.idy = 1.0 / ph.dy;
+  ph.idz = 1.0 / ph.dz;
+  ph.gamma = desc->gamma;
+  ph.gm1 = desc->gamma - 1.0;
+  ph.igm1 = 1.0 / (desc->gamma - 1.0);
+  ph.rmu = ph.gasrad ? desc->rgas / desc->mu : 0.0;
+  ph.arad = ph.gasrad ? desc->arad : 0.0;
+  ph.cg = ph.gasrad ? desc->rgas / ((desc->gamma - 1.0) * desc->mu) : 0.0;
+  ph.gz = desc->grav[2];
+  ph.newton_tol = desc->newton_tol;
+  ph.newton_maxit = desc->newton_maxit;
+  ph.xi_mode = desc->xi_mode;
+  ph.mach_cut = desc->mach_cut;
+  ph.imach_cut = desc->mach_cut > 0.0 ? 1.0 / desc->mach_cut : 0.0;
+  ph.dims_active[0] = desc->nx > 1;
+  ph.dims_active[1] = desc->ny > 1;
+  ph.dims_active[2] = desc->nz > 1;
+  c.ncell = (size_t)desc->nx * desc->ny * desc->nz;
+  c.nfz = (size_t)desc->nx * desc->ny * ph.nzf;
+  c.zseg = desc->nz < 32 ? desc->nz : 32;
+
+  auto cleanup = [&](hipError_t e, const char *what) {
+    g_init_err = std::string(what) + ": " + hipGetErrorString(e);
+    mhd_destroy(h);
+    return MHD_ERR_HIP;
+  };
+  hipError_t e;
+  for (int s = 0; s < 3; ++s) {
+    if ((e = hipMalloc(&c.U[s], sizeof(double) * 5 * c.ncell)) != hipSuccess)
+      return cleanup(e, "hipMalloc U");
+    if ((e = hipMalloc(&c.Bx[s], sizeof(double) * c.ncell)) != hipSuccess)
+      return cleanup(e, "hipMalloc Bx");
+    if ((e = hipMalloc(&c.By[s], sizeof(double) * c.ncell)) != hipSuccess)
+      return cleanup(e, "hipMalloc By");
+    if ((e = hipMalloc(&c.Bz[s], sizeof(double) * c.nfz)) != hipSuccess)
+      return cleanup(e, "hipMalloc Bz");
+    // the stage kernels never write the wall planes of a reflecting z:
+    // every rotating face buffer starts at zero
+    if ((e = hipMemsetAsync(c.Bz[s], 0, sizeof(double) * c.nfz, c.stream)) != hipSuccess)
+      return cleanup(e, "hipMemset Bz");
+  }
+  if (ph.gasrad)
+    for (int s = 0; s < 2; ++s)
+      if ((e = hipMalloc(&c.T[s], sizeof(double) * c.ncell)) != hipSuccess)
+        return cleanup(e, "hipMalloc T");
+  if ((e = hipMalloc(&c.bg_cc, sizeof(double) * 4 * ph.nz)) != hipSuccess)
+    return cleanup(e, "hipMalloc bg");
+  if ((e = hipMalloc(&c.bg_fz, sizeof(double) * 4 * ph.nzf)) != hipSuccess)
+    return cleanup(e, "hipMalloc bg");
+  if ((e = hipMemsetAsync(c.bg_cc, 0, sizeof(double) * 4 * ph.nz, c.stream)) != hipSuccess)
+    return cleanup(e, "hipMemset bg");
+  if ((e = hipMemsetAsync(c.bg_fz, 0, sizeof(double) * 4 * ph.nzf, c.stream)) != hipSuccess)
+    return cleanup(e, "hipMemset bg");
+  c.red_len = 16384;
+  if ((e = hipMalloc(&c.red, sizeof(double) * c.red_len)) != hipSuccess)
+    return cleanup(e, "hipMalloc red");
+  if ((e = hipMalloc(&c.dt_dev, sizeof(double))) != hipSuccess)
+    return cleanup(e, "hipMalloc dt");
+  if ((e = hipMalloc(&c.flags, sizeof(int))) != hipSuccess) return cleanup(e, "hipMalloc flags");
+  if ((e = hipMalloc(&c.nstats, sizeof(unsigned long long) * 3)) != hipSuccess)
+    return cleanup(e, "hipMalloc stats");
+  if ((e = hipMemsetAsync(c.flags, 0, sizeof(int), c.stream)) != hipSuccess)
+    return cleanup(e, "hipMemset flags");
+  if ((e = hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream)) != hipSuccess)
+    return cleanup(e, "hipMemset stats");
+  if ((e = hipStreamSynchronize(c.stream)) != hipSuccess) return cleanup(e, "sync");
+  *out = h;
+  return MHD_OK;
+}
+
+int mhd_destroy(mhd_ctx *h) {
+  if (!h) return MHD_OK;
+  mhd::Ctx &c = h->c;
+  (void)hipStreamSynchronize(c.stream);
+  for (int s = 0; s < 3; ++s) {
+    (void)hipFree(c.U[s]);
+    (void)hipFree(c.Bx[s]);
+    (void)hipFree(c.By[s]);
+    (void)hipFree(c.Bz[s]);
+  }
+  (void)hipFree(c.T[0]);
+  (void)hipFree(c.T[1]);
+  (void)hipFree(c.bg_cc);
+  (void)hipFree(c.bg_fz);
+  (void)hipFree(c.heat);
+  (void)hipFree(c.force);
+  (void)hipFree(c.red);
+  (void)hipFree(c.dt_dev);
+  (void)hipFree(c.flags);
+  (void)hipFree(c.nstats);
+  delete h;
+  return MHD_OK;
+}
+
+const char *mhd_last_error(const mhd_ctx *h) {
+  if (!h) return g_init_err.c_str();
+  return h->c.err.c_str();
+}
+
+int mhd_set_background(mhd_ctx *h, const double *w_cc, const double *w_fz) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!w_cc || !w_fz) return fail(h, MHD_ERR_ARG, "background arrays must not be NULL");
+  const int nz = c.ph.nz, nzf = c.ph.nzf;
+  for (int f = 0; f < 4; ++f) {
+    for (int k = 0; k < nz; ++k)
+      if (!std::isfinite(w_cc[f * nz + k])) return fail(h, MHD_ERR_ARG, "background not finite");
+    for (int k = 0; k < nzf; ++k)
+      if (!std::isfinite(w_fz[f * nzf + k])) return fail(h, MHD_ERR_ARG, "background not finite");
+  }
+  HIPCHK(h, hipMemcpyAsync(c.bg_cc, w_cc, sizeof(double) * 4 * nz, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(h, hipMemcpyAsync(c.bg_fz, w_fz, sizeof(double) * 4 * nzf, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  return MHD_OK;
+}
+
+int mhd_set_sources(mhd_ctx *h, const double *heat, const double *force, int32_t where) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  if (heat) {
+    if (!c.heat) HIPCHK(h, hipMalloc(&c.heat, sizeof(double) * c.ph.nz));
+    HIPCHK(h, hipMemcpyAsync(c.heat, heat, sizeof(double) * c.ph.nz, hipMemcpyHostToDevice, c.stream));
+  } else if (c.heat) {
+    HIPCHK(h, hipStreamSynchronize(c.stream));
+    (void)hipFree(c.heat);
+    c.heat = nullptr;
+  }
+  if (force) {
+    if (!c.force) HIPCHK(h, hipMalloc(&c.force, sizeof(double) * 3 * c.ncell));
+    HIPCHK(h, hipMemcpyAsync(c.force, force, sizeof(double) * 3 * c.ncell, kind_in(where), c.stream));
+  } else if (c.force) {
+    HIPCHK(h, hipStreamSynchronize(c.stream));
+    (void)hipFree(c.force);
+    c.force = nullptr;
+  }
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  return MHD_OK;
+}
+
+int mhd_set_state(mhd_ctx *h, const double *U, const double *Bx, const double *By,
+                  const double *Bz, const double *T, int32_t where) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!U || !Bx || !By || !Bz) return fail(h, MHD_ERR_ARG, "state arrays must not be NULL");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  const int s = c.cur;
+  HIPCHK(h, hipMemcpyAsync(c.U[s], U, sizeof(double) * 5 * c.ncell, kind_in(where), c.stream));
+  HIPCHK(h, hipMemcpyAsync(c.Bx[s], Bx, sizeof(double) * c.ncell, kind_in(where), c.stream));
+  HIPCHK(h, hipMemcpyAsync(c.By[s], By, sizeof(double) * c.ncell, kind_in(where), c.stream));
+  HIPCHK(h, hipMemcpyAsync(c.Bz[s], Bz, sizeof(double) * c.nfz, kind_in(where), c.stream));
+  if (c.ph.reflect) HIPCHK(h, mhd::launch_zero_walls(c, c.Bz[s]));
+  HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
+  if (c.ph.gasrad) {
+    if (T)
+      HIPCHK(h, hipMemcpyAsync(c.T[c.tcur], T, sizeof(double) * c.ncell, kind_in(where), c.stream));
+    else
+      HIPCHK(h, mhd::launch_init_temperature(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[c.tcur]));
+  }
+  c.have_state = true;
+  return latched(h);
+}
+
+static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
+  mhd::Ctx &c = h->c;
+  const int ns = c.d.rk_order == 3 ? 3 : 2;
+  const double(*co)[3] = c.d.rk_order == 3 ? kRK3 : kRK2;
+  const int n = c.cur;
+  const int a = (n + 1) % 3, b = (n + 2) % 3;
+  // stage outputs: RK2 n -> a -> b; RK3 n -> a -> b -> a
+  const int outs[3] = {a, b, a};
+  int in = n;
+  if (c.ph.gasrad)
+    HIPCHK(h, hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream));
+  for (int s = 0; s < ns; ++s) {
+    const int o = outs[s];
+    mhd::StagePtrs p;
+    p.Us = c.U[in];
+    p.Bxs = c.Bx[in];
+    p.Bys = c.By[in];
+    p.Bzs = c.Bz[in];
+    p.U0 = c.U[n];
+    p.Bx0 = c.Bx[n];
+    p.By0 = c.By[n];
+    p.Bz0 = c.Bz[n];
+    p.Uo = c.U[o];
+    p.Bxo = c.Bx[o];
+    p.Byo = c.By[o];
+    p.Bzo = c.Bz[o];
+    p.Tin = c.ph.gasrad ? c.T[c.tcur] : nullptr;
+    p.Tout = c.ph.gasrad ? c.T[1 - c.tcur] : nullptr;
+    p.bg_cc = c.bg_cc;
+    p.bg_fz = c.bg_fz;
+    p.heat = c.heat;
+    p.force = c.force;
+    p.dt_dev = dt_dev;
+    p.flags = c.flags;
+    p.newton_stats = c.nstats;
+    HIPCHK(h, mhd::launch_stage(c, p, co[s][0], co[s][1], co[s][2], dt_host));
+    if (c.ph.gasrad) c.tcur = 1 - c.tcur;
+    in = o;
+  }
+  c.cur = in;
+  return MHD_OK;
+}
+
+int mhd_step(mhd_ctx *h, double dt) {
+  if (!h) return MHD_ERR_ARG;
+  if (!h->c.have_state) return fail(h, MHD_ERR_STATE, "mhd_step before mhd_set_state");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, MHD_ERR_ARG, "dt must be finite and > 0");
+  return run_step(h, dt, nullptr);
+}
+
+int mhd_advance(mhd_ctx *h, double cfl, int32_t nsteps) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_advance before mhd_set_state");
+  if (!(cfl > 0.0) || !std::isfinite(cfl) || nsteps < 0)
+    return fail(h, MHD_ERR_ARG, "cfl must be > 0 and nsteps >= 0");
+  for (int s = 0; s < nsteps; ++s) {
+    const int n = c.cur;
+    HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
+                                       c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev));
+    int rc = run_step(h, 0.0, c.dt_dev);
+    if (rc) return rc;
+  }
+  return MHD_OK;
+}
+
+int mhd_compute_dt(mhd_ctx *h, double cfl, double *dt_out) {
+  if (!h || !dt_out) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_compute_dt before mhd_set_state");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, MHD_ERR_ARG, "cfl must be > 0");
+  const int n = c.cur;
+  HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
+                                     c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev));
+  double dt = 0.0;
+  HIPCHK(h, hipMemcpyAsync(&dt, c.dt_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  int rc = latched(h);
+  if (rc) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(h, MHD_ERR_UNPHYSICAL, "signal speed is not finite and positive");
+  *dt_out = dt;
+  return MHD_OK;
+}
+
+int mhd_get_state(mhd_ctx *h, double *U, double *Bx, double *By, double *Bz, double *T,
+                  int32_t where) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_get_state before mhd_set_state");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  const int s = c.cur;
+  if (U) HIPCHK(h, hipMemcpyAsync(U, c.U[s], sizeof(double) * 5 * c.ncell, kind_out(where), c.stream));
+  if (Bx) HIPCHK(h, hipMemcpyAsync(Bx, c.Bx[s], sizeof(double) * c.ncell, kind_out(where), c.stream));
+  if (By) HIPCHK(h, hipMemcpyAsync(By, c.By[s], sizeof(double) * c.ncell, kind_out(where), c.stream));
+  if (Bz) HIPCHK(h, hipMemcpyAsync(Bz, c.Bz[s], sizeof(double) * c.nfz, kind_out(where), c.stream));
+  if (T) {
+    if (!c.ph.gasrad) return fail(h, MHD_ERR_ARG, "T requested for the ideal-gas EOS");
+    HIPCHK(h, hipMemcpyAsync(T, c.T[c.tcur], sizeof(double) * c.ncell, kind_out(where), c.stream));
+  }
+  return latched(h);
+}
+
+int mhd_sync(mhd_ctx *h) {
+  if (!h) return MHD_ERR_ARG;
+  return latched(h);
+}
+
+int mhd_diagnostics(mhd_ctx *h, mhd_diag *out) {
+  if (!h || !out) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_diagnostics before mhd_set_state");
+  const int s = c.cur;
+  double v[9];
+  HIPCHK(h, mhd::launch_diagnostics(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], v));
+  std::memset(out, 0, sizeof(*out));
+  out->bface_max = v[2];
+  const double bm = v[2] > 0.0 ? v[2] : 1.0;
+  out->divb_max = v[0] / bm;
+  out->divb_l2 = std::sqrt(v[1] / (double)c.ncell) / bm;
+  for (int f = 0; f < 5; ++f) out->total[f] = v[3 + f];
+  out->bflux_x0 = v[8];
+  unsigned long long st[3] = {0, 0, 0};
+  int flags = 0;
+  HIPCHK(h, hipMemcpyAsync(st, c.nstats, sizeof(st), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(h, hipMemcpyAsync(&flags, c.flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  out->newton_iters = (int64_t)st[0];
+  out->newton_max = (int64_t)st[1];
+  out->fallbacks = (int64_t)st[2];
+  out->error_flags = flags;
+  return latched(h);
+}
+
+int mhd_launch_info(const mhd_ctx *h, int32_t *tile, int32_t *zseg, int32_t *blocks) {
+  if (!h) return MHD_ERR_ARG;
+  const mhd::Ctx &c = h->c;
+  if (tile) *tile = mhd::TB;
+  if (zseg) *zseg = c.zseg;
+  if (blocks)
+    *blocks = ((c.ph.nx + mhd::TB - 1) / mhd::TB) * ((c.ph.ny + mhd::TB - 1) / mhd::TB) *
+              ((c.ph.nz + c.zseg - 1) / c.zseg);
+  return MHD_OK;
+}
+
+}  // extern "C"

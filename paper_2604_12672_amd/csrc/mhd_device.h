@@ -1,0 +1,393 @@
+// mhd_device.h -- device functions of the MHD stage: EOS, cons -> prim,
+// reconstruction, the LHLLD flux in deviation form and the Contact-CT edge.
+//
+// Precision: R is the arithmetic type of reconstruction, Riemann flux and
+// EMFs (double, or float in the split mode).  Cons -> prim, the EOS Newton
+// solve and every accumulation run in double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mhd_internal.h"
+
+namespace mhd {
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+// ---------------------------------------------------------------------------
+
+template <typename R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+// split mode: hardware reciprocal (1 ulp), no IEEE division sequence
+template <> __device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <typename R> __device__ __forceinline__ R sqroot(R x);
+template <> __device__ __forceinline__ double sqroot<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqroot<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// gas + radiation EOS (Sect. 2.2, eqs. prad, erad)
+// e_int(T) = C_g T + (a/rho) T^4, P = rho (R/mu) T + a T^4 / 3
+// ---------------------------------------------------------------------------
+
+// Newton T <- T + de / c_v from the guess, stopping when |de| < tol e before
+// an update; a non-finite / non-positive guess or the iteration cap falls
+// back to a safeguarded Newton-bisection on the closed-form bracket
+// [min(e/(2C_g), (rho e/(2a))^1/4), min(e/C_g, (rho e/a)^1/4)].
+// Returns 0, or 2 when even the bracketed solve did not converge.
+__device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
+                                               double e, double tguess,
+                                               double &T, int &iters,
+                                               int &fallback) {
+  const double cg = ph.cg, ar = ph.arad / rho, tol = ph.newton_tol * e;
+  iters = 0;
+  fallback = 0;
+  double t = tguess;
+  if (t > 0.0 && t < INFINITY) {
+    for (int n = 0; n < ph.newton_maxit; ++n) {
+      const double t3 = t * t * t;
+      const double de = e - (cg * t + ar * t3 * t);
+      if (fabs(de) < tol) {
+        T = t;
+        iters = n;
+        return 0;
+      }
+      t = t + de / (cg + 4.0 * ar * t3);
+      iters = n + 1;
+      if (!(t > 0.0 && t < INFINITY)) break;
+    }
+  }
+  fallback = 1;
+  double lo = fmin(e / (2.0 * cg), sqrt(sqrt(e / (2.0 * ar))));
+  double hi = fmin(e / cg, sqrt(sqrt(e / ar)));
+  t = 0.5 * (lo + hi);
+  for (int n = 0; n < 400; ++n) {
+    const double t3 = t * t * t;
+    const double de = e - (cg * t + ar * t3 * t);
+    if (fabs(de) < tol) {
+      T = t;
+      return 0;
+    }
+    if (de > 0.0)
+      lo = t;
+    else
+      hi = t;
+    const double tn = t + de / (cg + 4.0 * ar * t3);
+    t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+    if (hi - lo <= 8.881784197001252e-16 * hi) {
+      T = t;
+      return 0;
+    }
+  }
+  T = t;
+  return 2;
+}
+
+// P, and the auxiliary indices gamma_e = P/(rho e) + 1, gamma_c = rho c_s^2/P
+// with c_s^2 = (dP/drho)_T + T (dP/dT)_rho^2 / (rho^2 c_v).
+__device__ __forceinline__ void eos_thermo(const Phys &ph, double rho, double e,
+                                           double T, double &P, double &ge,
+                                           double &gc) {
+  const double t3 = T * T * T;
+  P = rho * ph.rmu * T + ph.arad * t3 * T * (1.0 / 3.0);
+  const double cv = ph.cg + 4.0 * ph.arad * t3 / rho;
+  const double dpdt = rho * ph.rmu + (4.0 / 3.0) * ph.arad * t3;
+  const double cs2 = ph.rmu * T + T * dpdt * dpdt / (rho * rho * cv);
+  ge = P / (rho * e) + 1.0;
+  gc = rho * cs2 / P;
+}
+
+// ---------------------------------------------------------------------------
+// cons -> prim of one cell (double); deviation from the background
+// ---------------------------------------------------------------------------
+
+// Cell fields in the order used everywhere below.
+enum { Q_RHO = 0, Q_VX, Q_VY, Q_VZ, Q_P, Q_BX, Q_BY, Q_BZ, Q_GE, Q_GC };
+
+struct PrimOut {
+  double w[10];  // deviations of rho, P, gamma_e, gamma_c; full v, B_cc
+  double T;
+  int iters, fallback;
+  int bad;       // 1 unphysical, 2 EOS failure
+};
+
+// u: conserved (rho, m, E); b: cell-centred field; bg: background
+// (rho, P, gamma_e, gamma_c) of the cell's height.
+template <bool GR>
+__device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
+                                          const double b[3], double tguess,
+                                          const double bg[4], PrimOut &o) {
+  const double rho = u[0];
+  const double ir = 1.0 / rho;
+  const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+  const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const double e = (u[4] - 0.5 * rho * (vx * vx + vy * vy + vz * vz) - 0.5 * b2) * ir;
+  o.bad = (rho > 0.0 && e > 0.0 && e < INFINITY) ? 0 : 1;
+  double P, ge = ph.gamma, gc = ph.gamma;
+  o.T = 0.0;
+  o.iters = 0;
+  o.fallback = 0;
+  if (GR) {
+    double T = tguess;
+    if (!o.bad) {
+      if (eos_temperature(ph, rho, e, tguess, T, o.iters, o.fallback)) o.bad = 2;
+    }
+    o.T = T;
+    eos_thermo(ph, rho, e, T, P, ge, gc);
+  } else {
+    P = ph.gm1 * rho * e;
+  }
+  o.w[Q_RHO] = rho - bg[0];
+  o.w[Q_VX] = vx;
+  o.w[Q_VY] = vy;
+  o.w[Q_VZ] = vz;
+  o.w[Q_P] = P - bg[1];
+  o.w[Q_BX] = b[0];
+  o.w[Q_BY] = b[1];
+  o.w[Q_BZ] = b[2];
+  o.w[Q_GE] = ge - bg[2];
+  o.w[Q_GC] = gc - bg[3];
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction (Sect. 2.5): van Leer slope, harmonic form
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R vanleer(R a, R b) {
+  const R ab = a * b;
+  return ab > R(0) ? R(2) * ab * rcp<R>(a + b) : R(0);
+}
+
+// ---------------------------------------------------------------------------
+// LHLLD flux in deviation form (Sect. 2.6 and 2.8)
+//
+// One side of the face in the face frame (normal n, transverse t1, t2):
+// deviations of rho, P, gamma_e, gamma_c from the face background and the
+// full velocity and transverse field (the background has none).  The result
+// is F(W_L, W_R) - F(W_hat_f, W_hat_f) in the order {mass, mom_n, mom_t1,
+// mom_t2, energy, B_t1, B_t2}: with p~ = p_T - P_hat the background pressure
+// enters only through E + P_hat, so a zero deviation gives exactly zero.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Side {
+  R drho, vn, v1, v2, dp, b1, b2, dge, dgc;
+};
+
+template <typename R>
+struct FaceBg {
+  R rho, p, ge, gc;
+};
+
+template <typename R>
+struct SideQ {  // derived side quantities
+  R rho, vn, v1, v2, pt, b1, b2, E, vb;
+  R F[7];
+};
+
+template <typename R, bool GR>
+__device__ __forceinline__ void side_prep(const Side<R> &s, R bn,
+                                          const FaceBg<R> &bg, R gam, R igm1,
+                                          SideQ<R> &q, R &cf, R &mach2) {
+  q.rho = bg.rho + s.drho;
+  q.vn = s.vn;
+  q.v1 = s.v1;
+  q.v2 = s.v2;
+  q.b1 = s.b1;
+  q.b2 = s.b2;
+  const R P = bg.p + s.dp;
+  const R bn2 = bn * bn;
+  const R B2 = bn2 + s.b1 * s.b1 + s.b2 * s.b2;
+  const R v2 = s.vn * s.vn + s.v1 * s.v1 + s.v2 * s.v2;
+  const R ir = rcp<R>(q.rho);
+  R igm, gc;
+  if (GR) {
+    igm = rcp<R>(bg.ge + s.dge - R(1));
+    gc = bg.gc + s.dgc;
+  } else {
+    igm = igm1;
+    gc = gam;
+  }
+  q.pt = s.dp + R(0.5) * B2;  // p_T - P_hat
+  q.E = P * igm + R(0.5) * q.rho * v2 + R(0.5) * B2;
+  const R cs2 = gc * P * ir;
+  mach2 = v2 * rcp<R>(cs2);
+  const R a2b2 = cs2 + B2 * ir;
+  R disc = a2b2 * a2b2 - R(4) * cs2 * bn2 * ir;
+  disc = disc > R(0) ? disc : R(0);
+  cf = sqroot<R>(R(0.5) * (a2b2 + sqroot<R>(disc)));
+  q.vb = s.vn * bn + s.v1 * s.b1 + s.v2 * s.b2;
+  const R rv = q.rho * s.vn;
+  q.F[0] = rv;
+  q.F[1] = rv * s.vn + q.pt - bn2;
+  q.F[2] = rv * s.v1 - bn * s.b1;
+  q.F[3] = rv * s.v2 - bn * s.b2;
+  q.F[4] = (q.E + bg.p + q.pt) * s.vn - bn * q.vb;
+  q.F[5] = s.vn * s.b1 - bn * s.v1;
+  q.F[6] = s.vn * s.b2 - bn * s.v2;
+}
+
+template <typename R>
+struct Star {
+  R rho, v1, v2, b1, b2, vb;  // single-star state
+  R Fs[7];                    // single-star flux
+};
+
+// Single-star state and flux of one side: differences U* - U written so no
+// large number is subtracted from another (the split mode depends on it).
+template <typename R>
+__device__ __forceinline__ void star_side(const SideQ<R> &q, R S, R SM, R pst,
+                                          R bn, R bgp, Star<R> &st) {
+  const R isd = rcp<R>(S - SM);
+  const R f = q.rho * isd;
+  const R svn = S - q.vn, dvn = SM - q.vn;
+  st.rho = f * svn;          // rho*
+  const R drho = f * dvn;    // rho* - rho
+  const R bn2 = bn * bn;
+  const R D = q.rho * svn * (S - SM) - bn2;
+  R dv1 = R(0), dv2 = R(0), db1 = R(0), db2 = R(0);
+  // degenerate when |D| <= 1e-8 rho (S - v_n)^2: v_t and B_t unchanged
+  if (fabs(D) > R(1e-8) * q.rho * svn * svn) {
+    const R iD = rcp<R>(D);
+    const R qv = bn * dvn * iD;             // v*_t - v_t = -B_t qv
+    const R qb = q.rho * svn * dvn * iD;    // B*_t - B_t = B_t qb
+    dv1 = -q.b1 * qv;
+    dv2 = -q.b2 * qv;
+    db1 = q.b1 * qb;
+    db2 = q.b2 * qb;
+  }
+  st.v1 = q.v1 + dv1;
+  st.v2 = q.v2 + dv2;
+  st.b1 = q.b1 + db1;
+  st.b2 = q.b2 + db2;
+  st.vb = SM * bn + st.v1 * st.b1 + st.v2 * st.b2;
+  // E* - E = [(S_M - v_n)(E + P_hat) + p~* S_M - p~ v_n + B_n (v.B - v*.B*)] / (S - S_M)
+  const R dE = (dvn * (q.E + bgp) + pst * SM - q.pt * q.vn + bn * (q.vb - st.vb)) * isd;
+  st.Fs[0] = q.F[0] + S * drho;
+  // interface pressure carries the low-dissipation factor (through p~*)
+  st.Fs[1] = st.rho * SM * SM + pst - bn2;
+  st.Fs[2] = q.F[2] + S * (drho * st.v1 + q.rho * dv1);
+  st.Fs[3] = q.F[3] + S * (drho * st.v2 + q.rho * dv2);
+  st.Fs[4] = q.F[4] + S * dE;
+  st.Fs[5] = q.F[5] + S * db1;
+  st.Fs[6] = q.F[6] + S * db2;
+}
+
+template <typename R, bool GR>
+__device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
+                                        R bn, const FaceBg<R> &bg, R gam,
+                                        R igm1, int xi_mode, R mcut, R imcut,
+                                        R F[7]) {
+  SideQ<R> qL, qR;
+  R cfL, cfR, m2L, m2R;
+  side_prep<R, GR>(L, bn, bg, gam, igm1, qL, cfL, m2L);
+  side_prep<R, GR>(Rt, bn, bg, gam, igm1, qR, cfR, m2R);
+  const R cmax = cfL > cfR ? cfL : cfR;
+  const R SL = (qL.vn < qR.vn ? qL.vn : qR.vn) - cmax;
+  const R SR = (qL.vn > qR.vn ? qL.vn : qR.vn) + cmax;
+  if (R(0) <= SL) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = qL.F[c];
+    return;
+  }
+  if (SR < R(0)) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = qR.F[c];
+    return;
+  }
+  const R aL = (SL - qL.vn) * qL.rho, aR = (SR - qR.vn) * qR.rho;
+  const R iden = rcp<R>(aR - aL);
+  const R SM = (aR * qR.vn - aL * qL.vn - qR.pt + qL.pt) * iden;
+  // low-dissipation factor xi on the upwind term of p_T* (sonic Mach)
+  R xi = R(1);
+  if (xi_mode != MHD_XI_OFF) {
+    const R M = sqroot<R>(m2L > m2R ? m2L : m2R);
+    if (xi_mode == MHD_XI_LINEAR)
+      xi = M * imcut < R(1) ? M * imcut : R(1);
+    else
+      xi = M < mcut ? M : R(1);
+  }
+  const R pst = (aR * qL.pt - aL * qR.pt +
+                 xi * qL.rho * qR.rho * (SR - qR.vn) * (SL - qL.vn) * (qR.vn - qL.vn)) *
+                iden;
+  Star<R> sL, sR;
+  star_side<R>(qL, SL, SM, pst, bn, bg.p, sL);
+  star_side<R>(qR, SR, SM, pst, bn, bg.p, sR);
+  const R sqL = sqroot<R>(sL.rho), sqR = sqroot<R>(sR.rho);
+  const R abn = fabs(bn);
+  const R SsL = SM - abn * rcp<R>(sqL);
+  const R SsR = SM + abn * rcp<R>(sqR);
+  if (R(0) <= SsL) {  // S_L < 0 <= S*_L
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = sL.Fs[c];
+    return;
+  }
+  if (SsR < R(0)) {  // S*_R < 0 <= S_R
+#pragma unroll
+    for (int c = 0; c < 7; ++c) F[c] = sR.Fs[c];
+    return;
+  }
+  // double-star states (Alfven waves)
+  const R sg = bn >= R(0) ? R(1) : R(-1);
+  const R is = rcp<R>(sqL + sqR);
+  const R w1 = (sqL * sL.v1 + sqR * sR.v1 + (sR.b1 - sL.b1) * sg) * is;
+  const R w2 = (sqL * sL.v2 + sqR * sR.v2 + (sR.b2 - sL.b2) * sg) * is;
+  const R c1 = (sqL * sR.b1 + sqR * sL.b1 + sqL * sqR * (sR.v1 - sL.v1) * sg) * is;
+  const R c2 = (sqL * sR.b2 + sqR * sL.b2 + sqL * sqR * (sR.v2 - sL.v2) * sg) * is;
+  const R vbss = SM * bn + w1 * c1 + w2 * c2;
+  if (R(0) <= SM) {  // S*_L < 0 <= S_M
+    F[0] = sL.Fs[0];
+    F[1] = sL.Fs[1];
+    F[2] = sL.Fs[2] + SsL * sL.rho * (w1 - sL.v1);
+    F[3] = sL.Fs[3] + SsL * sL.rho * (w2 - sL.v2);
+    F[4] = sL.Fs[4] - SsL * sqL * (sL.vb - vbss) * sg;
+    F[5] = sL.Fs[5] + SsL * (c1 - sL.b1);
+    F[6] = sL.Fs[6] + SsL * (c2 - sL.b2);
+  } else {  // S_M < 0 <= S*_R
+    F[0] = sR.Fs[0];
+    F[1] = sR.Fs[1];
+    F[2] = sR.Fs[2] + SsR * sR.rho * (w1 - sR.v1);
+    F[3] = sR.Fs[3] + SsR * sR.rho * (w2 - sR.v2);
+    F[4] = sR.Fs[4] + SsR * sqR * (sR.vb - vbss) * sg;
+    F[5] = sR.Fs[5] + SsR * (c1 - sR.b1);
+    F[6] = sR.Fs[6] + SsR * (c2 - sR.b2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contact-CT edge EMF (Sect. 2.4; Gardiner & Stone 2005).
+// Edge of component c with a = c+1, b = c+2 (cyclic) at (a-1/2, b-1/2):
+//   Ea_b, Ea_bm : EMF on the a-faces at b and b-1
+//   Eb_a, Eb_am : EMF on the b-faces at a and a-1
+//   r_xy        : cell reference EMF -(v x B) at (a or a-1, b or b-1)
+//   m_*         : mass flux through the matching face (upwind direction)
+// Each face value is carried to the edge with the cell-side gradient of the
+// upwind cell; the mean of the four is the edge EMF.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R upwind(R m, R up, R dn) {
+  return m > R(0) ? up : (m < R(0) ? dn : R(0.5) * (up + dn));
+}
+
+template <typename R>
+__device__ __forceinline__ R ct_edge(R Ea_b, R Ea_bm, R Eb_a, R Eb_am, R r_ab,
+                                     R r_amb, R r_abm, R r_ambm, R m_ab,
+                                     R m_abm, R m_ba, R m_bam) {
+  const R d1 = upwind<R>(m_ab, Eb_am - r_amb, Eb_a - r_ab);
+  const R d2 = upwind<R>(m_abm, Eb_am - r_ambm, Eb_a - r_abm);
+  const R d3 = upwind<R>(m_ba, Ea_bm - r_abm, Ea_b - r_ab);
+  const R d4 = upwind<R>(m_bam, Ea_bm - r_ambm, Ea_b - r_amb);
+  return R(0.25) * ((Ea_b + Ea_bm) + (Eb_a + Eb_am)) + R(0.25) * ((d1 + d2) + (d3 + d4));
+}
+
+}  // namespace mhd

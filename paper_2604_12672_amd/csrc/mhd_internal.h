@@ -1,0 +1,90 @@
+// mhd_internal.h -- shared declarations of the HIP library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mhd.h"
+
+namespace mhd {
+
+// Stage-kernel tile: 16 x 16 threads, one cell column each; the inner
+// 14 x 14 columns are the outputs, the outer ring is the reconstruction
+// halo.  The block marches along z over a segment of ZSEG planes.
+constexpr int TT = 16;        // threads per tile edge
+constexpr int TB = TT - 2;    // output columns per tile edge
+constexpr int NTHREADS = TT * TT;
+
+// Physics and grid constants passed by value to every kernel.
+struct Phys {
+  int nx, ny, nz, nzf;
+  int reflect;        // z boundary: 1 = reflecting walls
+  int gasrad;         // 1 = gas+radiation EOS
+  double dx, dy, dz, idx, idy, idz;
+  double gamma, gm1, igm1;
+  double rmu, arad, cg;  // R/mu, a, C_g = R/((gamma-1) mu)
+  double gz;
+  double newton_tol;
+  int newton_maxit;
+  int xi_mode;
+  double mach_cut, imach_cut;
+  int dims_active[3];  // axis has more than one cell
+};
+
+// Pointers of one stage launch.
+struct StagePtrs {
+  const double *Us, *Bxs, *Bys, *Bzs;  // stage input U^(s)
+  const double *U0, *Bx0, *By0, *Bz0;  // step base U^(n) (read when a != 0)
+  double *Uo, *Bxo, *Byo, *Bzo;        // stage output
+  const double *Tin;                   // EOS guess (gas+radiation)
+  double *Tout;                        // EOS solution (owned cells)
+  const double *bg_cc, *bg_fz;         // [4][nz], [4][nzf]
+  const double *heat, *force;          // nullable
+  const double *dt_dev;                // device dt (nullable: use dt_host)
+  int *flags;                          // latched error flags
+  unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
+};
+
+struct Ctx {
+  mhd_grid_desc d;
+  Phys ph;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t ncell = 0, nfz = 0;
+  // three state buffers (rotated): U [5][n], Bx [n], By [n], Bz [nfz]
+  double *U[3] = {nullptr, nullptr, nullptr};
+  double *Bx[3] = {nullptr, nullptr, nullptr};
+  double *By[3] = {nullptr, nullptr, nullptr};
+  double *Bz[3] = {nullptr, nullptr, nullptr};
+  int cur = 0;  // index of the current state
+  double *T[2] = {nullptr, nullptr};
+  int tcur = 0;
+  double *bg_cc = nullptr, *bg_fz = nullptr;
+  double *heat = nullptr, *force = nullptr;
+  double *dt_dev = nullptr;       // [1]
+  double *red = nullptr;          // reduction scratch
+  size_t red_len = 0;
+  int *flags = nullptr;           // [1]
+  unsigned long long *nstats = nullptr;  // [3]
+  bool have_state = false;
+  int zseg = 32;
+  std::string err;
+};
+
+// launchers (mhd_kernels.hip)
+hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
+                        double cc, double dt_host);
+hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
+                               const double *By, const double *Bz,
+                               const double *T, double cfl, double *dt_dev);
+hipError_t launch_init_temperature(const Ctx &c, const double *U,
+                                   const double *Bx, const double *By,
+                                   const double *Bz, double *T);
+hipError_t launch_diagnostics(const Ctx &c, const double *U, const double *Bx,
+                              const double *By, const double *Bz,
+                              double *out /* host, 12 */);
+hipError_t launch_zero_walls(const Ctx &c, double *Bz);
+
+}  // namespace mhd

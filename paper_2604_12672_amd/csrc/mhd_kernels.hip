@@ -1,0 +1,780 @@
+// mhd_kernels.hip -- gfx950 kernels of the explicit MHD step.
+//
+// stage_kernel: one SSP-RK stage (Sect. 2.9) fused into one launch.  A block
+// owns a 14 x 14 column tile of the x-y plane and a segment of z planes; its
+// 16 x 16 threads hold one cell column each (the outer ring is the halo of
+// the three-cell reconstruction stencil, plus 64 ring cells two columns out
+// that only feed the x/y stencils).  The block marches up the segment; per
+// plane k it
+//   P1  converts plane k+2 to primitive deviations (EOS included) and
+//       reconstructs the z-faces of its own column (rolling registers),
+//   P2  solves the Riemann problems of the x- and y-faces of plane k+1 (cell
+//       plane staged in LDS) and of the z-face k+1/2,
+//   P3  updates the cells of plane k, accumulates the x/y flux divergence of
+//       plane k+1 and computes the Contact-CT edge EMFs E_z(k+1), E_x and
+//       E_y(k+1/2),
+//   P4  updates the faces B_x(k), B_y(k) and B_z(k+1/2).
+// Neighbour exchanges inside a 16-lane row use lane shuffles; exchanges
+// across rows use small LDS arrays.  Fluxes and EMFs on tile borders are
+// recomputed by both neighbouring blocks from identical inputs with the
+// same code, so every face and edge value is single-valued (div B stays at
+// round-off) without atomics or a global EMF array.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "mhd_device.h"
+#include "mhd_internal.h"
+
+namespace mhd {
+
+template <typename T>
+__device__ __forceinline__ T from_left(T v) {  // value of the lane at ci-1
+  return __shfl_up(v, 1, TT);
+}
+template <typename T>
+__device__ __forceinline__ T from_right(T v) {  // value of the lane at ci+1
+  return __shfl_down(v, 1, TT);
+}
+
+// z plane q -> stored plane and mirror flag (reflecting walls)
+__device__ __forceinline__ int zsource(const Phys &ph, int q, int &mirror) {
+  mirror = 0;
+  if (q >= 0 && q < ph.nz) return q;
+  if (!ph.reflect) return wrapi(q, ph.nz);
+  mirror = 1;
+  return q < 0 ? -1 - q : 2 * ph.nz - 1 - q;
+}
+// z face index f (0..nz for walls) -> stored face
+__device__ __forceinline__ int zface(const Phys &ph, int f) {
+  return ph.reflect ? f : wrapi(f, ph.nz);
+}
+
+struct CellLoad {
+  double u[5];
+  double b[3];
+  double bxl, byl;  // lower x / y faces of the cell (normal fields)
+  double tg;
+};
+
+__device__ __forceinline__ void load_cell(const Phys &ph, const StagePtrs &p,
+                                          int gi, int gip, int gj, int gjp,
+                                          int kk, int mirror, CellLoad &c) {
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t n = plane * ph.nz;
+  const size_t q = (size_t)kk * plane + (size_t)gj * ph.nx + gi;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) c.u[f] = p.Us[f * n + q];
+  c.bxl = p.Bxs[q];
+  c.byl = p.Bys[q];
+  const double bxr = p.Bxs[(size_t)kk * plane + (size_t)gj * ph.nx + gip];
+  const double byr = p.Bys[(size_t)kk * plane + (size_t)gjp * ph.nx + gi];
+  const int kp = ph.reflect ? kk + 1 : wrapi(kk + 1, ph.nz);
+  const double bzl = p.Bzs[(size_t)kk * plane + (size_t)gj * ph.nx + gi];
+  const double bzr = p.Bzs[(size_t)kp * plane + (size_t)gj * ph.nx + gi];
+  c.b[0] = 0.5 * (c.bxl + bxr);
+  c.b[1] = 0.5 * (c.byl + byr);
+  c.b[2] = 0.5 * (bzl + bzr);
+  c.tg = p.Tin ? p.Tin[q] : 0.0;
+  (void)mirror;
+}
+
+template <typename R, bool GR>
+struct Cfg {
+  static constexpr int NF = GR ? 10 : 8;  // cell fields kept per cell
+};
+
+// primitive deviations of one cell, as R, with the mirror image applied
+template <typename R, bool GR>
+__device__ __forceinline__ void prim_cell(const Phys &ph, const StagePtrs &p,
+                                          const CellLoad &c, int kk, int mirror,
+                                          R *w, PrimOut &o) {
+  double bg[4];
+  bg[0] = p.bg_cc[kk];
+  bg[1] = p.bg_cc[ph.nz + kk];
+  bg[2] = p.bg_cc[2 * ph.nz + kk];
+  bg[3] = p.bg_cc[3 * ph.nz + kk];
+  cons2prim<GR>(ph, c.u, c.b, c.tg, bg, o);
+  constexpr int NF = Cfg<R, GR>::NF;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) w[f] = (R)o.w[f];
+  if (mirror) {
+    w[Q_VZ] = -w[Q_VZ];
+    w[Q_BZ] = -w[Q_BZ];
+  }
+}
+
+// Face states of the sweep along `axis` from four consecutive cells m2..p1
+// (cells i-2, i-1, i, i+1 for the face i-1/2).
+template <typename R, bool GR>
+__device__ __forceinline__ void face_states(int axis, const R *m2, const R *m1,
+                                            const R *c0, const R *p1,
+                                            Side<R> &L, Side<R> &Rt) {
+  // face frame: axis 0: n=x t1=y t2=z; 1: n=y t1=z t2=x; 2: n=z t1=x t2=y
+  const int vn = Q_VX + axis, v1 = Q_VX + (axis + 1) % 3, v2 = Q_VX + (axis + 2) % 3;
+  const int b1 = Q_BX + (axis + 1) % 3, b2 = Q_BX + (axis + 2) % 3;
+  auto rec = [&](int f, R &l, R &r) {
+    const R sl = vanleer<R>(m1[f] - m2[f], c0[f] - m1[f]);
+    const R sr = vanleer<R>(c0[f] - m1[f], p1[f] - c0[f]);
+    l = m1[f] + R(0.5) * sl;
+    r = c0[f] - R(0.5) * sr;
+  };
+  rec(Q_RHO, L.drho, Rt.drho);
+  rec(vn, L.vn, Rt.vn);
+  rec(v1, L.v1, Rt.v1);
+  rec(v2, L.v2, Rt.v2);
+  rec(Q_P, L.dp, Rt.dp);
+  rec(b1, L.b1, Rt.b1);
+  rec(b2, L.b2, Rt.b2);
+  if (GR) {
+    rec(Q_GE, L.dge, Rt.dge);
+    rec(Q_GC, L.dgc, Rt.dgc);
+  } else {
+    L.dge = Rt.dge = L.dgc = Rt.dgc = R(0);
+  }
+}
+
+// face flux -> conserved order (rho, m_x, m_y, m_z, E)
+template <typename R>
+__device__ __forceinline__ void to_cons(int axis, const R F[7], R out[5]) {
+  out[0] = F[0];
+  out[1 + axis] = F[1];
+  out[1 + (axis + 1) % 3] = F[2];
+  out[1 + (axis + 2) % 3] = F[3];
+  out[4] = F[4];
+}
+
+template <typename R, bool GR>
+__global__ __launch_bounds__(NTHREADS) void stage_kernel(
+    Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
+    int zseg) {
+  constexpr int NF = Cfg<R, GR>::NF;
+  constexpr int LW = TT + 2;  // LDS plane edge: columns -2 .. 15
+  __shared__ R sW[NF][LW * LW];
+  __shared__ R sYF[5][NTHREADS];  // y-face conserved flux
+  __shared__ R sXE[2][NTHREADS];  // x-face E_z, mass flux
+  __shared__ R sZE[2][NTHREADS];  // z-face E_x, mass flux
+  __shared__ R sRX[2][NTHREADS];  // cell reference E_x, planes by parity
+  __shared__ R sRZ[NTHREADS];     // cell reference E_z of plane k+1
+  __shared__ R sEZ[2][NTHREADS];  // edge E_z, planes by parity
+  __shared__ R sEX[NTHREADS];     // edge E_x(k+1/2)
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TT, ty = tid / TT;
+  const int ci = tx - 1, cj = ty - 1;
+  const int X0 = blockIdx.x * TB, Y0 = blockIdx.y * TB;
+  const int z0 = blockIdx.z * zseg;
+  const int z1 = min(z0 + zseg, ph.nz);
+  const int gx = X0 + ci, gy = Y0 + cj;
+  const int gi = wrapi(gx, ph.nx), gip = wrapi(gx + 1, ph.nx);
+  const int gj = wrapi(gy, ph.ny), gjp = wrapi(gy + 1, ph.ny);
+  const bool owner = ci >= 0 && ci < TB && cj >= 0 && cj < TB && gx < ph.nx && gy < ph.ny;
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t ncell = plane * ph.nz;
+  const size_t colq = (size_t)gj * ph.nx + gi;
+
+  // ring cells two columns outside the tile (x/y stencils only)
+  const bool ring = tid < 64;
+  int rci = 0, rcj = 0;
+  if (tid < 16) {
+    rci = -2; rcj = tid - 1;
+  } else if (tid < 32) {
+    rci = TT - 1; rcj = tid - 17;
+  } else if (tid < 48) {
+    rci = tid - 33; rcj = -2;
+  } else {
+    rci = tid - 49; rcj = TT - 1;
+  }
+  const int rgi = wrapi(X0 + rci, ph.nx), rgip = wrapi(X0 + rci + 1, ph.nx);
+  const int rgj = wrapi(Y0 + rcj, ph.ny), rgjp = wrapi(Y0 + rcj + 1, ph.ny);
+  const int lw_own = (cj + 2) * LW + (ci + 2);
+  const int lw_ring = (rcj + 2) * LW + (rci + 2);
+
+  const double dt = p.dt_dev ? *p.dt_dev : dt_host;
+  const double cdt = cc * dt;
+  const R gam = (R)ph.gamma, igm1 = (R)ph.igm1;
+  const R mcut = (R)ph.mach_cut, imcut = (R)ph.imach_cut;
+
+  // rolling z-pipeline of the own column
+  R Wm[NF], Wc[NF], Wn[NF], Wr[NF];
+  Side<R> topk{}, topn{}, botn{};
+  // pipeline carries
+  R bxf_c = 0, byf_c = 0, bxf_n = 0, byf_n = 0;  // normal fields of plane k+1 / k+2
+  double acc[5] = {0, 0, 0, 0, 0};
+  R fzp[5] = {0, 0, 0, 0, 0};     // z-face conserved flux at k-1/2
+  R ex_prev = 0, ey_prev = 0;     // own edges E_x, E_y at k-1/2
+  R ez_cur = 0;                   // own edge E_z at plane k
+  R xf_ey_prev = 0, xf_m_prev = 0;  // own x-face E_y and mass flux, plane k
+  R yf_ex_prev = 0, yf_m_prev = 0;  // own y-face E_x and mass flux, plane k
+  R rx_prev = 0, ry_prev = 0;       // own cell reference E_x, E_y, plane k
+  unsigned long long nit = 0, nmax = 0, nfb = 0;
+  int bad = 0;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Wm[f] = Wc[f] = Wn[f] = Wr[f] = R(0);
+
+  for (int k = z0 - 4; k < z1; ++k) {
+    // ---------------- P1: primitives of plane q = k+2 ------------------
+    {
+      const int q = k + 2;
+      int mir;
+      const int kk = zsource(ph, q, mir);
+      CellLoad c;
+      load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+      PrimOut o;
+      prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o);
+      bxf_n = (R)c.bxl;
+      byf_n = (R)c.byl;
+      if (GR) {
+        const bool own_cell = owner && q >= z0 && q < z1;
+        if (own_cell) {
+          p.Tout[(size_t)kk * plane + colq] = o.T;
+          nit += o.iters;
+          nmax = o.iters > nmax ? o.iters : nmax;
+          nfb += o.fallback;
+        }
+      }
+      bad |= o.bad;
+      if (ring) {
+        int rmir;
+        const int rkk = zsource(ph, q, rmir);
+        CellLoad rc;
+        load_cell(ph, p, rgi, rgip, rgj, rgjp, rkk, rmir, rc);
+        PrimOut ro;
+        prim_cell<R, GR>(ph, p, rc, rkk, rmir, Wr, ro);
+        bad |= ro.bad;
+      }
+      // reconstruct the own column along z at cell k+1
+      if (k >= z0 - 2) {
+        // slope of cell k+1 from (Wm = k, Wc = k+1, Wn = k+2): bottom (R
+        // state of face k+1/2) and top (L state of face k+3/2)
+        auto rz = [&](int f, R &bot, R &top) {
+          const R s = vanleer<R>(Wc[f] - Wm[f], Wn[f] - Wc[f]);
+          bot = Wc[f] - R(0.5) * s;
+          top = Wc[f] + R(0.5) * s;
+        };
+        rz(Q_RHO, botn.drho, topn.drho);
+        rz(Q_VZ, botn.vn, topn.vn);
+        rz(Q_VX, botn.v1, topn.v1);
+        rz(Q_VY, botn.v2, topn.v2);
+        rz(Q_P, botn.dp, topn.dp);
+        rz(Q_BX, botn.b1, topn.b1);
+        rz(Q_BY, botn.b2, topn.b2);
+        if (GR) {
+          rz(Q_GE, botn.dge, topn.dge);
+          rz(Q_GC, botn.dgc, topn.dgc);
+        } else {
+          botn.dge = topn.dge = botn.dgc = topn.dgc = R(0);
+        }
+      }
+    }
+
+    // ---------------- P2: fluxes of plane k+1 and face k+1/2 -----------
+    R fx[7], fy[7], fz[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) fx[c] = fy[c] = fz[c] = R(0);
+    R rx = 0, ry = 0, rz_ = 0;
+    if (k >= z0 - 2) {
+      int mir;
+      const int kc = zsource(ph, k + 1, mir);
+      FaceBg<R> bgc;
+      bgc.rho = (R)p.bg_cc[kc];
+      bgc.p = (R)p.bg_cc[ph.nz + kc];
+      bgc.ge = (R)p.bg_cc[2 * ph.nz + kc];
+      bgc.gc = (R)p.bg_cc[3 * ph.nz + kc];
+      // x-face ci-1/2 of row cj (stencil clamped inside the LDS plane)
+      {
+        const int i0 = ci - 2 < -2 ? -2 : ci - 2;
+        const int row = (cj + 2) * LW + 2;
+        R a0[NF], a1[NF], a2[NF], a3[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          a0[f] = sW[f][row + i0];
+          a1[f] = sW[f][row + i0 + 1];
+          a2[f] = sW[f][row + i0 + 2];
+          a3[f] = sW[f][row + i0 + 3];
+        }
+        Side<R> L, Rt;
+        face_states<R, GR>(0, a0, a1, a2, a3, L, Rt);
+        riemann<R, GR>(L, Rt, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
+      }
+      // y-face cj-1/2 of column ci
+      {
+        const int j0 = cj - 2 < -2 ? -2 : cj - 2;
+        const int col = ci + 2;
+        R a0[NF], a1[NF], a2[NF], a3[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          a0[f] = sW[f][(j0 + 2) * LW + col];
+          a1[f] = sW[f][(j0 + 3) * LW + col];
+          a2[f] = sW[f][(j0 + 4) * LW + col];
+          a3[f] = sW[f][(j0 + 5) * LW + col];
+        }
+        Side<R> L, Rt;
+        face_states<R, GR>(1, a0, a1, a2, a3, L, Rt);
+        riemann<R, GR>(L, Rt, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
+      }
+      // cell reference EMF -(v x B) of plane k+1 (own column)
+      rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);
+      ry = -(Wc[Q_VZ] * Wc[Q_BX] - Wc[Q_VX] * Wc[Q_BZ]);
+      rz_ = -(Wc[Q_VX] * Wc[Q_BY] - Wc[Q_VY] * Wc[Q_BX]);
+      if (k >= z0 - 1) {
+        // z-face k+1/2: L = top of cell k, R = bottom of cell k+1
+        const int fzi = zface(ph, k + 1);
+        FaceBg<R> bgf;
+        const int nzf = ph.nzf;
+        bgf.rho = (R)p.bg_fz[fzi];
+        bgf.p = (R)p.bg_fz[nzf + fzi];
+        bgf.ge = (R)p.bg_fz[2 * nzf + fzi];
+        bgf.gc = (R)p.bg_fz[3 * nzf + fzi];
+        const R bzn = (R)p.Bzs[(size_t)fzi * plane + colq];
+        riemann<R, GR>(topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut, imcut, fz);
+      }
+      R fyc[5];
+      to_cons<R>(1, fy, fyc);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) sYF[f][tid] = fyc[f];
+      sXE[0][tid] = -fx[5];  // x-face E_z = -F_x[B_y]
+      sXE[1][tid] = fx[0];
+      sZE[0][tid] = fz[6];   // z-face E_x = +F_z[B_y]
+      sZE[1][tid] = fz[0];
+      sRX[(k + 1) & 1][tid] = rx;
+      sRZ[tid] = rz_;
+    }
+    __syncthreads();
+
+    // ---------------- P3: cells of plane k, divergence, edge EMFs -------
+    R fxc[5], fzc[5];
+    to_cons<R>(0, fx, fxc);
+    to_cons<R>(2, fz, fzc);
+    R fxr[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) fxr[f] = from_right(fxc[f]);
+    // neighbour data at ci-1 (same row)
+    const R yf_ez_l = from_left(fy[6]);   // y-face E_z = +F_y[B_x]
+    const R yf_m_l = from_left(fy[0]);
+    const R rz_l = from_left(rz_);
+    const R zf_ey_l = from_left(-fz[5]);  // z-face E_y = -F_z[B_x]
+    const R zf_m_l = from_left(fz[0]);
+    const R ry_l = from_left(ry);
+    const R ry_prev_l = from_left(ry_prev);
+    const int tdn = tid >= TT ? tid - TT : tid;            // (ci, cj-1)
+    const int tdl = tid >= TT + 1 ? tid - TT - 1 : tid;    // (ci-1, cj-1)
+    const int tup = tid + TT < NTHREADS ? tid + TT : tid;  // (ci, cj+1)
+    R ex_new = 0, ey_new = 0, ez_new = 0;
+    if (k >= z0 - 1) {
+      // cells of plane k
+      if (k >= z0 && owner) {
+        const size_t q = (size_t)k * plane + colq;
+        double us[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + q];
+        double r[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) r[f] = acc[f] + ((double)fzc[f] - (double)fzp[f]) * ph.idz;
+        // sources S - S_hat: gravity on the density deviation, rho g.v,
+        // heating, forcing (Sect. 2.1, eq. wb2)
+        double s1 = 0.0, s2 = 0.0, s3 = (us[0] - p.bg_cc[k]) * ph.gz, s4 = us[3] * ph.gz;
+        if (p.heat) s4 += p.heat[k];
+        if (p.force) {
+          const double f0 = p.force[q], f1 = p.force[ncell + q], f2 = p.force[2 * ncell + q];
+          s1 += us[0] * f0;
+          s2 += us[0] * f1;
+          s3 += us[0] * f2;
+          s4 += us[1] * f0 + us[2] * f1 + us[3] * f2;
+        }
+        r[1] -= s1;
+        r[2] -= s2;
+        r[3] -= s3;
+        r[4] -= s4;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          double v = cb * us[f] - cdt * r[f];
+          if (ca != 0.0) v += ca * p.U0[f * ncell + q];
+          p.Uo[f * ncell + q] = v;
+        }
+      }
+      // x/y divergence of plane k+1
+      R fyu[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) fyu[f] = sYF[f][tup];
+      R fyc[5];
+      to_cons<R>(1, fy, fyc);
+#pragma unroll
+      for (int f = 0; f < 5; ++f)
+        acc[f] = ((double)fxr[f] - (double)fxc[f]) * ph.idx +
+                 ((double)fyu[f] - (double)fyc[f]) * ph.idy;
+      // E_z at (ci-1/2, cj-1/2, k+1)
+      ez_new = ct_edge<R>(-fx[5], sXE[0][tdn], fy[6], yf_ez_l, rz_, rz_l, sRZ[tdn],
+                          sRZ[tdl], fx[0], sXE[1][tdn], fy[0], yf_m_l);
+      // E_x at (ci, cj-1/2, k+1/2): a = y (y-faces at planes k+1, k),
+      // b = z (z-faces at cj, cj-1)
+      const int s1 = (k + 1) & 1, s0 = k & 1;
+      ex_new = ct_edge<R>(-fy[5], yf_ex_prev, fz[6], sZE[0][tdn], rx, sRX[s1][tdn], rx_prev,
+                          sRX[s0][tdn], fy[0], yf_m_prev, fz[0], sZE[1][tdn]);
+      // E_y at (ci-1/2, cj, k+1/2): a = z (z-faces at ci, ci-1), b = x
+      // (x-faces at planes k+1, k)
+      ey_new = ct_edge<R>(-fz[5], zf_ey_l, fx[6], xf_ey_prev, ry, ry_prev, ry_l, ry_prev_l,
+                          fz[0], zf_m_l, fx[0], xf_m_prev);
+      if (ph.reflect && (k + 1 == 0 || k + 1 == ph.nz)) {
+        ex_new = R(0);
+        ey_new = R(0);
+      }
+      sEZ[(k + 1) & 1][tid] = ez_new;
+      sEX[tid] = ex_new;
+    }
+    // stage the cell plane k+2 for the next x/y sweep
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sW[f][lw_own] = Wn[f];
+    if (ring) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sW[f][lw_ring] = Wr[f];
+    }
+    __syncthreads();
+
+    // ---------------- P4: faces B_x(k), B_y(k), B_z(k+1/2) --------------
+    const R ez_r = from_right(ez_cur);
+    const R ey_r = from_right(ey_new);
+    if (k >= z0 && owner) {
+      const size_t q = (size_t)k * plane + colq;
+      const double ez_u = (double)sEZ[k & 1][tup];
+      const double rbx = (ez_u - (double)ez_cur) * ph.idy -
+                         ((double)ey_new - (double)ey_prev) * ph.idz;
+      const double rby = ((double)ex_new - (double)ex_prev) * ph.idz -
+                         ((double)ez_r - (double)ez_cur) * ph.idx;
+      double bx = cb * p.Bxs[q] - cdt * rbx;
+      double by = cb * p.Bys[q] - cdt * rby;
+      if (ca != 0.0) {
+        bx += ca * p.Bx0[q];
+        by += ca * p.By0[q];
+      }
+      p.Bxo[q] = bx;
+      p.Byo[q] = by;
+    }
+    if (k >= z0 - 1 && k + 1 < z1 && owner && !(ph.reflect && k + 1 == 0)) {
+      const size_t qf = (size_t)(k + 1) * plane + colq;
+      const double ex_u = (double)sEX[tup];
+      const double rbz = ((double)ey_r - (double)ey_new) * ph.idx -
+                         (ex_u - (double)ex_new) * ph.idy;
+      double bz = cb * p.Bzs[qf] - cdt * rbz;
+      if (ca != 0.0) bz += ca * p.Bz0[qf];
+      p.Bzo[qf] = bz;
+    }
+
+    // ---------------- shift the pipeline --------------------------------
+    ez_cur = ez_new;
+    ex_prev = ex_new;
+    ey_prev = ey_new;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) fzp[f] = fzc[f];
+    xf_ey_prev = fx[6];
+    xf_m_prev = fx[0];
+    yf_ex_prev = -fy[5];
+    yf_m_prev = fy[0];
+    rx_prev = rx;
+    ry_prev = ry;
+    topk = topn;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      Wm[f] = Wc[f];
+      Wc[f] = Wn[f];
+    }
+    bxf_c = bxf_n;
+    byf_c = byf_n;
+  }
+  if (bad) atomicOr(p.flags, bad);
+  if (GR) {
+    // block totals of the Newton statistics
+    __shared__ unsigned long long s_it[NTHREADS / 64], s_fb[NTHREADS / 64], s_mx[NTHREADS / 64];
+    unsigned long long a = nit, f = nfb, m = nmax;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      f += __shfl_xor(f, o);
+      unsigned long long mo = __shfl_xor(m, o);
+      m = mo > m ? mo : m;
+    }
+    if ((tid & 63) == 0) {
+      s_it[tid >> 6] = a;
+      s_fb[tid >> 6] = f;
+      s_mx[tid >> 6] = m;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long A = 0, Fb = 0, M = 0;
+      for (int w = 0; w < NTHREADS / 64; ++w) {
+        A += s_it[w];
+        Fb += s_fb[w];
+        M = s_mx[w] > M ? s_mx[w] : M;
+      }
+      atomicAdd(&p.newton_stats[0], A);
+      atomicMax(&p.newton_stats[1], M);
+      atomicAdd(&p.newton_stats[2], Fb);
+    }
+  }
+}
+
+hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
+                        double cc, double dt_host) {
+  const Phys &ph = c.ph;
+  dim3 grid((ph.nx + TB - 1) / TB, (ph.ny + TB - 1) / TB, (ph.nz + c.zseg - 1) / c.zseg);
+  dim3 block(NTHREADS);
+  const bool gr = ph.gasrad != 0;
+  const bool split = c.d.precision == MHD_PREC_SPLIT;
+  if (split) {
+    if (gr)
+      hipLaunchKernelGGL((stage_kernel<float, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
+                         dt_host, c.zseg);
+    else
+      hipLaunchKernelGGL((stage_kernel<float, false>), grid, block, 0, c.stream, ph, p, a, b,
+                         cc, dt_host, c.zseg);
+  } else {
+    if (gr)
+      hipLaunchKernelGGL((stage_kernel<double, true>), grid, block, 0, c.stream, ph, p, a, b,
+                         cc, dt_host, c.zseg);
+    else
+      hipLaunchKernelGGL((stage_kernel<double, false>), grid, block, 0, c.stream, ph, p, a, b,
+                         cc, dt_host, c.zseg);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CFL time step (eq. cfl): per-cell signal speed, block max, final max
+// ---------------------------------------------------------------------------
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 2048;
+
+template <bool GR>
+__global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
+    Phys ph, const double *__restrict__ U, const double *__restrict__ Bx,
+    const double *__restrict__ By, const double *__restrict__ Bz,
+    const double *__restrict__ T, double *__restrict__ partial, int *flags) {
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t n = plane * ph.nz;
+  double smax = 0.0;
+  int bad = 0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % ph.nx);
+    const int j = (int)((q / ph.nx) % ph.ny);
+    const int k = (int)(q / plane);
+    const int ip = i + 1 == ph.nx ? 0 : i + 1;
+    const int jp = j + 1 == ph.ny ? 0 : j + 1;
+    const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
+    double u[5], b[3];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = U[f * n + q];
+    b[0] = 0.5 * (Bx[q] + Bx[q - i + ip]);
+    b[1] = 0.5 * (By[q] + By[q + (size_t)(jp - j) * ph.nx]);
+    b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
+    const double zero[4] = {0, 0, 0, 0};
+    PrimOut o;
+    cons2prim<GR>(ph, u, b, T ? T[q] : 0.0, zero, o);
+    bad |= o.bad;
+    const double rho = u[0];
+    const double P = o.w[Q_P];
+    const double a2 = o.w[Q_GC] * P / rho;
+    const double b2 = (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]) / rho;
+    const double v[3] = {o.w[Q_VX], o.w[Q_VY], o.w[Q_VZ]};
+    const double ids[3] = {ph.idx, ph.idy, ph.idz};
+    double sum = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      if (!ph.dims_active[s]) continue;
+      const double bs2 = b[s] * b[s] / rho;
+      double disc = (a2 + b2) * (a2 + b2) - 4.0 * a2 * bs2;
+      disc = disc > 0.0 ? disc : 0.0;
+      const double cf = sqrt(0.5 * ((a2 + b2) + sqrt(disc)));
+      sum += (fabs(v[s]) + cf) * ids[s];
+    }
+    smax = sum > smax ? sum : smax;
+    if (!(sum < INFINITY)) bad |= 1;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double t = __shfl_xor(smax, o);
+    smax = t > smax ? t : smax;
+  }
+  __shared__ double sm[RED_THREADS / 64];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = smax;
+  if (bad) atomicOr(flags, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < RED_THREADS / 64; ++w) m = sm[w] > m ? sm[w] : m;
+    partial[blockIdx.x] = m;
+  }
+}
+
+__global__ void finish_dt_kernel(const double *__restrict__ partial, int nb,
+                                 double cfl, double *dt_out, double *smax_out) {
+  __shared__ double sm[RED_THREADS];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = partial[i] > m ? partial[i] : m;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] = sm[threadIdx.x + s] > sm[threadIdx.x] ? sm[threadIdx.x + s] : sm[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *smax_out = sm[0];
+    *dt_out = cfl / sm[0];
+  }
+}
+
+hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
+                               const double *By, const double *Bz,
+                               const double *T, double cfl, double *dt_dev) {
+  const size_t n = c.ncell;
+  int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
+  nb = nb < RED_BLOCKS ? nb : RED_BLOCKS;
+  if (c.ph.gasrad)
+    hipLaunchKernelGGL(signal_speed_kernel<true>, dim3(nb), dim3(RED_THREADS), 0, c.stream, c.ph,
+                       U, Bx, By, Bz, T, c.red, c.flags);
+  else
+    hipLaunchKernelGGL(signal_speed_kernel<false>, dim3(nb), dim3(RED_THREADS), 0, c.stream,
+                       c.ph, U, Bx, By, Bz, T, c.red, c.flags);
+  hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(RED_THREADS), 0, c.stream, c.red, nb, cfl,
+                     dt_dev, c.red + RED_BLOCKS);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial temperature (bracketed solve) for the previous-T guess
+// ---------------------------------------------------------------------------
+
+__global__ void init_temperature_kernel(Phys ph, const double *__restrict__ U,
+                                        const double *__restrict__ Bx,
+                                        const double *__restrict__ By,
+                                        const double *__restrict__ Bz,
+                                        double *__restrict__ T, int *flags) {
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t n = plane * ph.nz;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % ph.nx);
+    const int j = (int)((q / ph.nx) % ph.ny);
+    const int k = (int)(q / plane);
+    const int ip = i + 1 == ph.nx ? 0 : i + 1;
+    const int jp = j + 1 == ph.ny ? 0 : j + 1;
+    const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
+    double u[5], b[3];
+    for (int f = 0; f < 5; ++f) u[f] = U[f * n + q];
+    b[0] = 0.5 * (Bx[q] + Bx[q - i + ip]);
+    b[1] = 0.5 * (By[q] + By[q + (size_t)(jp - j) * ph.nx]);
+    b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
+    const double zero[4] = {0, 0, 0, 0};
+    PrimOut o;
+    cons2prim<true>(ph, u, b, NAN, zero, o);
+    if (o.bad) atomicOr(flags, o.bad);
+    T[q] = o.T;
+  }
+}
+
+hipError_t launch_init_temperature(const Ctx &c, const double *U,
+                                   const double *Bx, const double *By,
+                                   const double *Bz, double *T) {
+  int nb = (int)((c.ncell + 255) / 256);
+  nb = nb < 4096 ? nb : 4096;
+  hipLaunchKernelGGL(init_temperature_kernel, dim3(nb), dim3(256), 0, c.stream, c.ph, U, Bx, By,
+                     Bz, T, c.flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: div B (eq. divb), |B_face| max, conservation totals
+// ---------------------------------------------------------------------------
+
+constexpr int DIAG_BLOCKS = 1024;
+constexpr int NDIAG = 9;  // divb max, divb^2 sum, |B| max, 5 totals, bflux_x0
+
+__global__ __launch_bounds__(256) void diag_kernel(Phys ph, const double *__restrict__ U,
+                                                   const double *__restrict__ Bx,
+                                                   const double *__restrict__ By,
+                                                   const double *__restrict__ Bz,
+                                                   double *__restrict__ part) {
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t n = plane * ph.nz;
+  const double dmin = fmin(ph.dx, fmin(ph.dy, ph.dz));
+  double v[NDIAG];
+  for (int f = 0; f < NDIAG; ++f) v[f] = 0.0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(q % ph.nx);
+    const int j = (int)((q / ph.nx) % ph.ny);
+    const int k = (int)(q / plane);
+    const int ip = i + 1 == ph.nx ? 0 : i + 1;
+    const int jp = j + 1 == ph.ny ? 0 : j + 1;
+    const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
+    const double bxl = Bx[q], bxr = Bx[q - i + ip];
+    const double byl = By[q], byr = By[q + (size_t)(jp - j) * ph.nx];
+    const double bzl = Bz[q], bzr = Bz[(size_t)kp * plane + (q - (size_t)k * plane)];
+    const double d = ((bxr - bxl) * ph.idx + (byr - byl) * ph.idy + (bzr - bzl) * ph.idz) * dmin;
+    v[0] = fmax(v[0], fabs(d));
+    v[1] += d * d;
+    v[2] = fmax(v[2], fmax(fabs(bxl), fmax(fabs(byl), fabs(bzl))));
+    if (ph.reflect && k == ph.nz - 1) v[2] = fmax(v[2], fabs(bzr));
+    for (int f = 0; f < 5; ++f) v[3 + f] += U[f * n + q];
+    if (i == 0) v[8] += bxl;
+  }
+  __shared__ double sm[NDIAG][256];
+  for (int f = 0; f < NDIAG; ++f) sm[f][threadIdx.x] = v[f];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sm[0][threadIdx.x] = fmax(sm[0][threadIdx.x], sm[0][threadIdx.x + s]);
+      sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + s]);
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+      for (int f = 3; f < NDIAG; ++f) sm[f][threadIdx.x] += sm[f][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NDIAG) part[(size_t)threadIdx.x * DIAG_BLOCKS + blockIdx.x] = sm[threadIdx.x][0];
+}
+
+hipError_t launch_diagnostics(const Ctx &c, const double *U, const double *Bx,
+                              const double *By, const double *Bz, double *out) {
+  hipLaunchKernelGGL(diag_kernel, dim3(DIAG_BLOCKS), dim3(256), 0, c.stream, c.ph, U, Bx, By, Bz,
+                     c.red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  static thread_local double host[NDIAG * DIAG_BLOCKS];
+  e = hipMemcpyAsync(host, c.red, sizeof(double) * NDIAG * DIAG_BLOCKS, hipMemcpyDeviceToHost,
+                     c.stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return e;
+  // fixed-order host reduction of the block partials
+  for (int f = 0; f < NDIAG; ++f) {
+    long double s = 0.0L;
+    double m = 0.0;
+    for (int b = 0; b < DIAG_BLOCKS; ++b) {
+      const double x = host[(size_t)f * DIAG_BLOCKS + b];
+      if (f == 0 || f == 2)
+        m = x > m ? x : m;
+      else
+        s += x;
+    }
+    out[f] = (f == 0 || f == 2) ? m : (double)s;
+  }
+  return hipSuccess;
+}
+
+__global__ void zero_walls_kernel(double *Bz, size_t plane, size_t top) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < plane;
+       q += (size_t)gridDim.x * blockDim.x) {
+    Bz[q] = 0.0;
+    Bz[top + q] = 0.0;
+  }
+}
+
+hipError_t launch_zero_walls(const Ctx &c, double *Bz) {
+  const size_t plane = (size_t)c.ph.nx * c.ph.ny;
+  int nb = (int)((plane + 255) / 256);
+  nb = nb < 1024 ? nb : 1024;
+  hipLaunchKernelGGL(zero_walls_kernel, dim3(nb), dim3(256), 0, c.stream, Bz, plane,
+                     plane * (size_t)c.ph.nz);
+  return hipGetLastError();
+}
+
+}  // namespace mhd

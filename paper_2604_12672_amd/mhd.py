@@ -1,0 +1,275 @@
+"""Python binding of libmhd.so (the C ABI in include/mhd.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  Arrays may be numpy arrays (host) or torch CUDA
+tensors (device, FP64, contiguous); the context launches on the torch
+stream current at creation unless another stream is given.  The library
+must have been built (``paper_2604_12672_amd.build``); importing this
+module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhd.so")
+
+HOST, DEVICE = 0, 1
+PREC_FP64, PREC_SPLIT = 0, 1
+GUESS_PREV_T, GUESS_MLP = 0, 1
+BC_PERIODIC, BC_REFLECT = 0, 1
+
+ERRORS = {-1: "MHD_ERR_ARG", -2: "MHD_ERR_NO_DEVICE", -3: "MHD_ERR_HIP",
+          -4: "MHD_ERR_UNPHYSICAL", -5: "MHD_ERR_EOS", -6: "MHD_ERR_STATE"}
+
+
+class MHDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("bc", C.c_int32 * 3),
+        ("eos", C.c_int32), ("gamma", C.c_double), ("mu", C.c_double),
+        ("rgas", C.c_double), ("arad", C.c_double), ("grav", C.c_double * 3),
+        ("rk_order", C.c_int32), ("precision", C.c_int32), ("eos_guess", C.c_int32),
+        ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("mach_cut", C.c_double),
+        ("xi_mode", C.c_int32),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("divb_max", C.c_double), ("divb_l2", C.c_double), ("bface_max", C.c_double),
+        ("total", C.c_double * 5), ("bflux_x0", C.c_double), ("newton_iters", C.c_int64),
+        ("newton_max", C.c_int64), ("fallbacks", C.c_int64), ("error_flags", C.c_int32),
+    ]
+
+
+EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_state",
+           "mhd_compute_dt", "mhd_step", "mhd_advance", "mhd_get_state", "mhd_sync",
+           "mhd_diagnostics", "mhd_last_error", "mhd_destroy", "mhd_launch_info"]
+
+_lib = None
+
+
+def load():
+    """Load libmhd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2604_12672_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.mhd_init_grid.argtypes = [C.POINTER(GridDesc), vp, C.POINTER(vp)]
+    L.mhd_set_background.argtypes = [vp, vp, vp]
+    L.mhd_set_sources.argtypes = [vp, vp, vp, C.c_int32]
+    L.mhd_set_state.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
+    L.mhd_compute_dt.argtypes = [vp, C.c_double, C.POINTER(C.c_double)]
+    L.mhd_step.argtypes = [vp, C.c_double]
+    L.mhd_advance.argtypes = [vp, C.c_double, C.c_int32]
+    L.mhd_get_state.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
+    L.mhd_sync.argtypes = [vp]
+    L.mhd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
+    L.mhd_last_error.argtypes = [vp]
+    L.mhd_last_error.restype = C.c_char_p
+    L.mhd_destroy.argtypes = [vp]
+    L.mhd_launch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]
+    for name in EXPORTS:
+        getattr(L, name).restype = C.c_int if name != "mhd_last_error" else C.c_char_p
+    _lib = L
+    return L
+
+
+def make_desc(params: dict, precision=PREC_FP64, eos_guess=GUESS_PREV_T) -> GridDesc:
+    p = params
+    d = GridDesc()
+    d.nx, d.ny, d.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    lo, hi = p.get("lo", (0.0, 0.0, 0.0)), p.get("hi", (1.0, 1.0, 1.0))
+    for a in range(3):
+        d.lo[a], d.hi[a] = float(lo[a]), float(hi[a])
+    d.bc[0] = d.bc[1] = BC_PERIODIC
+    d.bc[2] = int(p.get("bcz", BC_PERIODIC))
+    d.eos = int(p.get("eos", 0))
+    d.gamma = float(p.get("gamma", 5.0 / 3.0))
+    d.mu = float(p.get("mu", 0.6))
+    d.rgas = float(p.get("rgas", 0.0))
+    d.arad = float(p.get("arad", 0.0))
+    d.grav[0], d.grav[1], d.grav[2] = 0.0, 0.0, float(p.get("gz", 0.0))
+    d.rk_order = int(p.get("rk_order", 2))
+    d.precision = int(precision)
+    d.eos_guess = int(eos_guess)
+    d.newton_tol = float(p.get("newton_tol", 1e-11))
+    d.newton_maxit = int(p.get("newton_maxit", 50))
+    d.mach_cut = float(p.get("mach_cut", 0.6))
+    d.xi_mode = int(p.get("xi_mode", 0))
+    return d
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, where):
+    """(pointer, where) of an array argument; None passes NULL."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        import torch
+        assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous(), \
+            "device arrays must be contiguous float64 CUDA tensors"
+        if where not in (None, DEVICE):
+            raise ValueError("mixed host/device arguments")
+        return C.c_void_p(a.data_ptr())
+    a = np.asarray(a)
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "host arrays must be C-contiguous float64"
+    if where not in (None, HOST):
+        raise ValueError("mixed host/device arguments")
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _where(*arrays):
+    kinds = {DEVICE if _is_torch(a) else HOST for a in arrays if a is not None}
+    if len(kinds) > 1:
+        raise ValueError("mixed host/device arguments")
+    return kinds.pop() if kinds else HOST
+
+
+class Grid:
+    """One library context: a grid, its device state and its stream."""
+
+    def __init__(self, params: dict, precision=PREC_FP64, eos_guess=GUESS_PREV_T, stream=None):
+        L = load()
+        self._L = L
+        self.params = dict(params)
+        self.desc = make_desc(params, precision, eos_guess)
+        if stream is None:
+            try:
+                import torch
+                stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+            except ImportError:
+                stream = 0
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.mhd_init_grid(C.byref(self.desc), C.c_void_p(stream), C.byref(h))
+        if rc != 0:
+            raise MHDError(rc, L.mhd_last_error(None).decode())
+        self._h = h
+        nz = self.desc.nz
+        self.nzf = nz + 1 if self.desc.bc[2] == BC_REFLECT else nz
+        self.shape = (nz, self.desc.ny, self.desc.nx)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise MHDError(rc, self._L.mhd_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mhd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- inputs ----------------------------------------------------------
+    def set_background(self, bg_cc, bg_fz):
+        bg_cc = np.ascontiguousarray(bg_cc, dtype=np.float64)
+        bg_fz = np.ascontiguousarray(bg_fz, dtype=np.float64)
+        assert bg_cc.shape == (4, self.shape[0]) and bg_fz.shape == (4, self.nzf)
+        self._check(self._L.mhd_set_background(self._h, _ptr(bg_cc, HOST), _ptr(bg_fz, HOST)))
+
+    def set_sources(self, heat=None, force=None):
+        if heat is not None:
+            heat = np.ascontiguousarray(heat, dtype=np.float64)
+            assert heat.shape == (self.shape[0],)
+        w = _where(force)
+        if force is not None and not _is_torch(force):
+            force = np.ascontiguousarray(force, dtype=np.float64)
+        if force is not None:
+            assert tuple(force.shape) == (3,) + self.shape
+        self._check(self._L.mhd_set_sources(self._h, _ptr(heat, HOST), _ptr(force, w), w))
+
+    def set_state(self, U, Bx, By, Bz, T=None):
+        w = _where(U, Bx, By, Bz, T)
+        self._check_shapes(U, Bx, By, Bz, T)
+        self._check(self._L.mhd_set_state(self._h, _ptr(U, w), _ptr(Bx, w), _ptr(By, w),
+                                          _ptr(Bz, w), _ptr(T, w), w))
+
+    def _check_shapes(self, U, Bx, By, Bz, T):
+        sh = self.shape
+        assert tuple(U.shape) == (5,) + sh, U.shape
+        assert tuple(Bx.shape) == sh and tuple(By.shape) == sh
+        assert tuple(Bz.shape) == (self.nzf,) + sh[1:]
+        if T is not None:
+            assert tuple(T.shape) == sh
+
+    def load(self, w, guess=True):
+        """Set state, background and sources from a workloads.Workload."""
+        if w.bg_cc is not None:
+            self.set_background(w.bg_cc, w.bg_fz)
+        if w.heat is not None or w.force is not None:
+            self.set_sources(w.heat, w.force)
+        self.set_state(w.U, w.Bx, w.By, w.Bz, w.T if guess else None)
+
+    # -- stepping --------------------------------------------------------
+    def step(self, dt):
+        self._check(self._L.mhd_step(self._h, float(dt)))
+
+    def advance(self, cfl, nsteps):
+        self._check(self._L.mhd_advance(self._h, float(cfl), int(nsteps)))
+
+    def compute_dt(self, cfl):
+        out = C.c_double(0.0)
+        self._check(self._L.mhd_compute_dt(self._h, float(cfl), C.byref(out)))
+        return out.value
+
+    def sync(self):
+        self._check(self._L.mhd_sync(self._h))
+
+    # -- outputs ---------------------------------------------------------
+    def get_state(self, out=None, with_T=False):
+        """Return the state as numpy arrays, or copy into `out` (a dict of
+        arrays or tensors with the keys U, Bx, By, Bz[, T])."""
+        if out is None:
+            sh = self.shape
+            out = {"U": np.empty((5,) + sh), "Bx": np.empty(sh), "By": np.empty(sh),
+                   "Bz": np.empty((self.nzf,) + sh[1:])}
+            if with_T:
+                out["T"] = np.empty(sh)
+        T = out.get("T")
+        w = _where(out["U"], out["Bx"], out["By"], out["Bz"], T)
+        self._check_shapes(out["U"], out["Bx"], out["By"], out["Bz"], T)
+        self._check(self._L.mhd_get_state(self._h, _ptr(out["U"], w), _ptr(out["Bx"], w),
+                                          _ptr(out["By"], w), _ptr(out["Bz"], w), _ptr(T, w), w))
+        return out
+
+    def diagnostics(self):
+        d = Diag()
+        self._check(self._L.mhd_diagnostics(self._h, C.byref(d)))
+        return {"divb_max": d.divb_max, "divb_l2": d.divb_l2, "bface_max": d.bface_max,
+                "total": list(d.total), "bflux_x0": d.bflux_x0,
+                "newton_iters": d.newton_iters, "newton_max": d.newton_max,
+                "fallbacks": d.fallbacks, "error_flags": d.error_flags}
+
+    def launch_info(self):
+        t, z, b = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self._L.mhd_launch_info(self._h, C.byref(t), C.byref(z), C.byref(b)))
+        return {"tile": t.value, "zseg": z.value, "blocks": b.value}

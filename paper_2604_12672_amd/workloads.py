@@ -498,3 +498,82 @@ def config(idx: int, n: int | None = None):
     if idx == 4:
         return turbulence_box(n or 384)
     raise ValueError(idx)
+
+
+def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2, eos=EOS_IDEAL):
+    """Smooth random state on [0,1]^3 (parity tests on ragged grids): rho and
+    P = 1 + 0.2 x (sum of a few low Fourier modes), v likewise with
+    amplitude amp_v, face B from a random edge vector potential (amplitude
+    amp_b) so that div B = 0 to round-off.  With a reflecting z the vector
+    potential's x/y components vanish on the walls."""
+    if eos == EOS_GASRAD:
+        p = gasrad_params(nx, ny, nz, bcz=bcz)
+    else:
+        p = base_params(nx, ny, nz, bcz=bcz)
+    rng = np.random.default_rng(seed)
+    xc, yc, zc, xf, yf, zf, d = _centres(p)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+
+    def field(scale):
+        f = np.zeros_like(X)
+        for _ in range(4):
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            kz = k[2] if bcz == BC_PERIODIC else 0
+            f += rng.normal() * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + kz * Z) + ph)
+        return scale * f / 4.0
+
+    rho = 1.0 + np.abs(field(0.2)) + 0.05
+    P = 1.0 + np.abs(field(0.2)) + 0.05
+    v = [field(amp_v) for _ in range(3)]
+    if bcz == BC_REFLECT:
+        v[2] *= np.sin(np.pi * Z)
+    nzf = nz + 1 if bcz == BC_REFLECT else nz
+    # edge vector potential on (x_i / x_{i-1/2}, y, z_{k-1/2}) positions
+    def ax_at(Xe, Ye, Ze, wall):
+        f = np.zeros_like(Xe)
+        for _ in range(3):
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            if bcz == BC_PERIODIC:
+                f += rng.normal() * np.cos(2 * np.pi * (k[0] * Xe + k[1] * Ye + k[2] * Ze) + ph)
+            else:
+                f += rng.normal() * np.cos(2 * np.pi * (k[0] * Xe + k[1] * Ye) + ph) * \
+                    np.sin(np.pi * max(1, abs(int(k[2]))) * Ze)
+        if bcz == BC_REFLECT and wall:
+            f[0] = 0.0
+            f[-1] = 0.0
+        return amp_b * f
+    xe = np.concatenate([xf, [xf[-1] + d[0]]])
+    ye = np.concatenate([yf, [yf[-1] + d[1]]])
+    ze = np.concatenate([zf, [zf[-1] + d[2]]]) if bcz == BC_PERIODIC else zf
+    # A_x at (x_i, y_{j-1/2}, z_{k-1/2}); A_y at (x_{i-1/2}, y_j, z_{k-1/2});
+    # A_z at (x_{i-1/2}, y_{j-1/2}, z_k)
+    Ze1, Ye1, Xe1 = np.meshgrid(ze, ye, xc, indexing="ij")
+    Ax = ax_at(Xe1, Ye1, Ze1, True)
+    Ze2, Ye2, Xe2 = np.meshgrid(ze, yc, xe, indexing="ij")
+    Ay = ax_at(Xe2, Ye2, Ze2, True)
+    Ze3, Ye3, Xe3 = np.meshgrid(zc, ye, xe, indexing="ij")
+    Az = ax_at(Xe3, Ye3, Ze3, False)
+    if bcz == BC_PERIODIC:
+        # periodic images: last edge equals the first
+        Ax[-1] = Ax[0]; Ax[:, -1] = Ax[:, 0]
+        Ay[-1] = Ay[0]; Ay[:, :, -1] = Ay[:, :, 0]
+        Az[:, -1] = Az[:, 0]; Az[:, :, -1] = Az[:, :, 0]
+    Bx = (Az[:, 1:, :nx] - Az[:, :ny, :nx]) / d[1] - (Ay[1:nz + 1, :, :nx] - Ay[:nz, :, :nx]) / d[2]
+    By = (Ax[1:nz + 1, :ny, :] - Ax[:nz, :ny, :]) / d[2] - (Az[:, :ny, 1:] - Az[:, :ny, :nx]) / d[0]
+    Bz = (Ay[:nzf, :, 1:] - Ay[:nzf, :, :nx]) / d[0] - (Ax[:nzf, 1:, :] - Ax[:nzf, :ny, :]) / d[1]
+    Bx, By, Bz = (np.ascontiguousarray(a) for a in (Bx, By, Bz))
+    T = None
+    eint = None
+    if eos == EOS_GASRAD:
+        T = 10.0 ** (6.0 + field(1.0))
+        rho = 10.0 ** field(1.0)
+        P, eint = gasrad_forward(p, rho, T)
+        cs = np.sqrt(P.mean() / rho.mean())
+        v = [vv * cs for vv in v]
+        bx, by, bz = _cell_field(p, Bx, By, Bz)
+        s = math.sqrt(2.0 * P.mean() / (10.0 * np.mean(bx * bx + by * by + bz * bz)))
+        Bx, By, Bz = Bx * s, By * s, Bz * s
+    U = _conserved(p, rho, v[0], v[1], v[2], P, Bx, By, Bz, eint=eint)
+    return Workload("smooth_box", p, U, Bx, By, Bz, T=T)

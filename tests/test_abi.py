@@ -1,0 +1,109 @@
+"""The C-ABI library loads, exports every symbol include/mhd.h declares,
+its struct layouts match the binding, and argument validation rejects bad
+descriptors before touching a device (no compute calls here)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2604_12672_amd import mhd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mhd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mhd.LIB_PATH):
+        from paper_2604_12672_amd import build
+        build.build()
+    return mhd.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mhd_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only", mhd.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (mhd_[a-z_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+    assert set(mhd.EXPORTS) <= set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mhd.h"
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("mhd_grid_desc %zu\n", sizeof(mhd_grid_desc));
+  printf("mhd_diag %zu\n", sizeof(mhd_diag));
+  O(mhd_grid_desc, lo); O(mhd_grid_desc, bc); O(mhd_grid_desc, eos);
+  O(mhd_grid_desc, gamma); O(mhd_grid_desc, grav); O(mhd_grid_desc, rk_order);
+  O(mhd_grid_desc, newton_tol); O(mhd_grid_desc, mach_cut); O(mhd_grid_desc, xi_mode);
+  O(mhd_diag, total); O(mhd_diag, newton_iters); O(mhd_diag, error_flags);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in lines if l)
+    assert int(got["mhd_grid_desc"]) == C.sizeof(mhd.GridDesc)
+    assert int(got["mhd_diag"]) == C.sizeof(mhd.Diag)
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            cls = mhd.GridDesc if t == "mhd_grid_desc" else mhd.Diag
+            assert getattr(cls, f).offset == int(val), key
+
+
+def _desc(**kw):
+    p = dict(nx=8, ny=8, nz=8)
+    p.update(kw)
+    return mhd.make_desc(p)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(nz=-3), dict(gamma=1.0), dict(bcz=7), dict(rk_order=4),
+    dict(eos=5), dict(hi=(1.0, 0.0, 1.0)), dict(bcz=1, nz=1),
+    dict(eos=1, rgas=0.0), dict(xi_mode=9), dict(mach_cut=0.0),
+])
+def test_descriptor_validation(lib, bad):
+    d = _desc(**bad)
+    h = C.c_void_p()
+    rc = lib.mhd_init_grid(C.byref(d), None, C.byref(h))
+    assert rc == -1, (bad, rc)
+    assert not h.value
+    assert lib.mhd_last_error(None)
+
+
+def test_precision_and_guess_validation(lib):
+    d = _desc()
+    d.precision = 5
+    h = C.c_void_p()
+    assert lib.mhd_init_grid(C.byref(d), None, C.byref(h)) == -1
+    d = _desc()
+    d.grav[0] = 1.0
+    assert lib.mhd_init_grid(C.byref(d), None, C.byref(h)) == -1
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.mhd_step(None, 0.1) == -1
+    assert lib.mhd_advance(None, 0.4, 1) == -1
+    assert lib.mhd_sync(None) == -1
+    assert lib.mhd_destroy(None) == 0
+    assert lib.mhd_init_grid(None, None, None) == -1
