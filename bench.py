@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--only", choices=["fp64", "split"], default=None)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -136,6 +138,14 @@ def main():
         res[name] = dict(wall=wall, stage_ms=stage_ms, diag=diag, info=info)
         log(f"bench: {name} {wall / args.steps * 1e3:.3f} ms/step, stage {stage_ms:.3f} ms, "
             f"divB {diag['divb_max']:.2e}")
+    if args.calib_copy:
+        # plain streaming kernel of known size: reads 2^30 bytes, writes 2^30
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 1 GiB done")
     main_name = "fp64" if "fp64" in res else "split"
     r = res[main_name]
     ms = r["wall"] / args.steps * 1e3

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -198,7 +199,15 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   ph.dims_active[2] = desc->nz > 1;
   c.ncell = (size_t)desc->nx * desc->ny * desc->nz;
   c.nfz = (size_t)desc->nx * desc->ny * ph.nzf;
-  c.zseg = desc->nz < 32 ? desc->nz : 32;
+  // z planes per stage block: a longer segment re-reads fewer halo planes
+  // (4 extra per segment), a shorter one gives more blocks; MHD_ZSEG
+  // overrides the default for tuning
+  c.zseg = 32;
+  if (const char *zs = std::getenv("MHD_ZSEG")) {
+    const int v = std::atoi(zs);
+    if (v >= 1 && v <= 4096) c.zseg = v;
+  }
+  if (c.zseg > desc->nz) c.zseg = desc->nz;
 
   auto cleanup = [&](hipError_t e, const char *what) {
     g_init_err = std::string(what) + ": " + hipGetErrorString(e);

@@ -17,13 +17,31 @@ namespace mhd {
 // ---------------------------------------------------------------------------
 
 template <typename R> __device__ __forceinline__ R rcp(R x);
-template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+// FP64: hardware reciprocal refined by two Newton steps (about 1 ulp; the
+// IEEE division sequence costs twice as many instructions)
+template <> __device__ __forceinline__ double rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 // split mode: hardware reciprocal (1 ulp), no IEEE division sequence
 template <> __device__ __forceinline__ float rcp<float>(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
 template <typename R> __device__ __forceinline__ R sqroot(R x);
-template <> __device__ __forceinline__ double sqroot<double>(double x) { return sqrt(x); }
+// FP64: reciprocal square root refined by Goldschmidt/Newton steps; x >= 0
+template <> __device__ __forceinline__ double sqroot<double>(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
 template <> __device__ __forceinline__ float sqroot<float>(float x) {
   return __builtin_amdgcn_sqrtf(x);
 }
@@ -237,51 +255,46 @@ __device__ __forceinline__ void side_prep(const Side<R> &s, R bn,
 }
 
 template <typename R>
-struct Star {
-  R rho, v1, v2, b1, b2, vb;  // single-star state
-  R Fs[7];                    // single-star flux
+struct Star {  // single-star state of one side, as differences from U
+  R rho, drho;     // rho*, rho* - rho
+  R dv1, dv2;      // v*_t - v_t
+  R db1, db2;      // B*_t - B_t
+  R dE;            // E* - E
+  R vb;            // v* . B*
 };
 
-// Single-star state and flux of one side: differences U* - U written so no
-// large number is subtracted from another (the split mode depends on it).
+// Single-star state of one side (Miyoshi & Kusano 2005), with every
+// difference U* - U written so that no large number is subtracted from
+// another (the split mode depends on it).
 template <typename R>
 __device__ __forceinline__ void star_side(const SideQ<R> &q, R S, R SM, R pst,
                                           R bn, R bgp, Star<R> &st) {
   const R isd = rcp<R>(S - SM);
   const R f = q.rho * isd;
   const R svn = S - q.vn, dvn = SM - q.vn;
-  st.rho = f * svn;          // rho*
-  const R drho = f * dvn;    // rho* - rho
-  const R bn2 = bn * bn;
-  const R D = q.rho * svn * (S - SM) - bn2;
-  R dv1 = R(0), dv2 = R(0), db1 = R(0), db2 = R(0);
+  st.rho = f * svn;
+  st.drho = f * dvn;
+  const R D = q.rho * svn * (S - SM) - bn * bn;
   // degenerate when |D| <= 1e-8 rho (S - v_n)^2: v_t and B_t unchanged
-  if (fabs(D) > R(1e-8) * q.rho * svn * svn) {
-    const R iD = rcp<R>(D);
-    const R qv = bn * dvn * iD;             // v*_t - v_t = -B_t qv
-    const R qb = q.rho * svn * dvn * iD;    // B*_t - B_t = B_t qb
-    dv1 = -q.b1 * qv;
-    dv2 = -q.b2 * qv;
-    db1 = q.b1 * qb;
-    db2 = q.b2 * qb;
-  }
-  st.v1 = q.v1 + dv1;
-  st.v2 = q.v2 + dv2;
-  st.b1 = q.b1 + db1;
-  st.b2 = q.b2 + db2;
-  st.vb = SM * bn + st.v1 * st.b1 + st.v2 * st.b2;
+  const bool nondeg = fabs(D) > R(1e-8) * q.rho * svn * svn;
+  const R iD = rcp<R>(D);
+  const R qv = nondeg ? bn * dvn * iD : R(0);           // v*_t - v_t = -B_t qv
+  const R qb = nondeg ? q.rho * svn * dvn * iD : R(0);  // B*_t - B_t = B_t qb
+  st.dv1 = -q.b1 * qv;
+  st.dv2 = -q.b2 * qv;
+  st.db1 = q.b1 * qb;
+  st.db2 = q.b2 * qb;
+  st.vb = SM * bn + (q.v1 + st.dv1) * (q.b1 + st.db1) + (q.v2 + st.dv2) * (q.b2 + st.db2);
   // E* - E = [(S_M - v_n)(E + P_hat) + p~* S_M - p~ v_n + B_n (v.B - v*.B*)] / (S - S_M)
-  const R dE = (dvn * (q.E + bgp) + pst * SM - q.pt * q.vn + bn * (q.vb - st.vb)) * isd;
-  st.Fs[0] = q.F[0] + S * drho;
-  // interface pressure carries the low-dissipation factor (through p~*)
-  st.Fs[1] = st.rho * SM * SM + pst - bn2;
-  st.Fs[2] = q.F[2] + S * (drho * st.v1 + q.rho * dv1);
-  st.Fs[3] = q.F[3] + S * (drho * st.v2 + q.rho * dv2);
-  st.Fs[4] = q.F[4] + S * dE;
-  st.Fs[5] = q.F[5] + S * db1;
-  st.Fs[6] = q.F[6] + S * db2;
+  st.dE = (dvn * (q.E + bgp) + pst * SM - q.pt * q.vn + bn * (q.vb - st.vb)) * isd;
 }
 
+template <typename R>
+__device__ __forceinline__ R sel(bool c, R a, R b) { return c ? a : b; }
+
+// LHLLD flux in deviation form.  The fan is resolved without branches: the
+// side of the contact that holds x/t = 0 (S_M >= 0: left) is selected, and
+// its single- and double-star fluxes are built once.
 template <typename R, bool GR>
 __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
                                         R bn, const FaceBg<R> &bg, R gam,
@@ -294,16 +307,6 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   const R cmax = cfL > cfR ? cfL : cfR;
   const R SL = (qL.vn < qR.vn ? qL.vn : qR.vn) - cmax;
   const R SR = (qL.vn > qR.vn ? qL.vn : qR.vn) + cmax;
-  if (R(0) <= SL) {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) F[c] = qL.F[c];
-    return;
-  }
-  if (SR < R(0)) {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) F[c] = qR.F[c];
-    return;
-  }
   const R aL = (SL - qL.vn) * qL.rho, aR = (SR - qR.vn) * qR.rho;
   const R iden = rcp<R>(aR - aL);
   const R SM = (aR * qR.vn - aL * qL.vn - qR.pt + qL.pt) * iden;
@@ -326,40 +329,57 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   const R abn = fabs(bn);
   const R SsL = SM - abn * rcp<R>(sqL);
   const R SsR = SM + abn * rcp<R>(sqR);
-  if (R(0) <= SsL) {  // S_L < 0 <= S*_L
-#pragma unroll
-    for (int c = 0; c < 7; ++c) F[c] = sL.Fs[c];
-    return;
-  }
-  if (SsR < R(0)) {  // S*_R < 0 <= S_R
-#pragma unroll
-    for (int c = 0; c < 7; ++c) F[c] = sR.Fs[c];
-    return;
-  }
-  // double-star states (Alfven waves)
+  // double-star transverse velocity and field (Alfven waves)
   const R sg = bn >= R(0) ? R(1) : R(-1);
   const R is = rcp<R>(sqL + sqR);
-  const R w1 = (sqL * sL.v1 + sqR * sR.v1 + (sR.b1 - sL.b1) * sg) * is;
-  const R w2 = (sqL * sL.v2 + sqR * sR.v2 + (sR.b2 - sL.b2) * sg) * is;
-  const R c1 = (sqL * sR.b1 + sqR * sL.b1 + sqL * sqR * (sR.v1 - sL.v1) * sg) * is;
-  const R c2 = (sqL * sR.b2 + sqR * sL.b2 + sqL * sqR * (sR.v2 - sL.v2) * sg) * is;
+  const R vL1 = qL.v1 + sL.dv1, vL2 = qL.v2 + sL.dv2, vR1 = qR.v1 + sR.dv1, vR2 = qR.v2 + sR.dv2;
+  const R bL1 = qL.b1 + sL.db1, bL2 = qL.b2 + sL.db2, bR1 = qR.b1 + sR.db1, bR2 = qR.b2 + sR.db2;
+  const R w1 = (sqL * vL1 + sqR * vR1 + (bR1 - bL1) * sg) * is;
+  const R w2 = (sqL * vL2 + sqR * vR2 + (bR2 - bL2) * sg) * is;
+  const R c1 = (sqL * bR1 + sqR * bL1 + sqL * sqR * (vR1 - vL1) * sg) * is;
+  const R c2 = (sqL * bR2 + sqR * bL2 + sqL * sqR * (vR2 - vL2) * sg) * is;
   const R vbss = SM * bn + w1 * c1 + w2 * c2;
-  if (R(0) <= SM) {  // S*_L < 0 <= S_M
-    F[0] = sL.Fs[0];
-    F[1] = sL.Fs[1];
-    F[2] = sL.Fs[2] + SsL * sL.rho * (w1 - sL.v1);
-    F[3] = sL.Fs[3] + SsL * sL.rho * (w2 - sL.v2);
-    F[4] = sL.Fs[4] - SsL * sqL * (sL.vb - vbss) * sg;
-    F[5] = sL.Fs[5] + SsL * (c1 - sL.b1);
-    F[6] = sL.Fs[6] + SsL * (c2 - sL.b2);
-  } else {  // S_M < 0 <= S*_R
-    F[0] = sR.Fs[0];
-    F[1] = sR.Fs[1];
-    F[2] = sR.Fs[2] + SsR * sR.rho * (w1 - sR.v1);
-    F[3] = sR.Fs[3] + SsR * sR.rho * (w2 - sR.v2);
-    F[4] = sR.Fs[4] + SsR * sqR * (sR.vb - vbss) * sg;
-    F[5] = sR.Fs[5] + SsR * (c1 - sR.b1);
-    F[6] = sR.Fs[6] + SsR * (c2 - sR.b2);
+  // side holding x/t = 0
+  const bool lf = SM >= R(0);
+  const R S = sel(lf, SL, SR), Ss = sel(lf, SsL, SsR), sq = sel(lf, sqL, sqR);
+  const R rho = sel(lf, qL.rho, qR.rho);
+  const R rs = sel(lf, sL.rho, sR.rho), drs = sel(lf, sL.drho, sR.drho);
+  const R dv1 = sel(lf, sL.dv1, sR.dv1), dv2 = sel(lf, sL.dv2, sR.dv2);
+  const R db1 = sel(lf, sL.db1, sR.db1), db2 = sel(lf, sL.db2, sR.db2);
+  const R dE = sel(lf, sL.dE, sR.dE), vbs = sel(lf, sL.vb, sR.vb);
+  const R vs1 = sel(lf, vL1, vR1), vs2 = sel(lf, vL2, vR2);
+  const R bs1 = sel(lf, bL1, bR1), bs2 = sel(lf, bL2, bR2);
+  R Fa[7];
+#pragma unroll
+  for (int c = 0; c < 7; ++c) Fa[c] = sel(lf, qL.F[c], qR.F[c]);
+  // single-star flux F* = F + S (U* - U); the interface pressure p~*
+  // carries the low-dissipation factor into the normal momentum
+  R Fs[7];
+  Fs[0] = Fa[0] + S * drs;
+  Fs[1] = rs * SM * SM + pst - bn * bn;
+  Fs[2] = Fa[2] + S * (drs * vs1 + rho * dv1);
+  Fs[3] = Fa[3] + S * (drs * vs2 + rho * dv2);
+  Fs[4] = Fa[4] + S * dE;
+  Fs[5] = Fa[5] + S * db1;
+  Fs[6] = Fa[6] + S * db2;
+  // double-star flux F** = F* + S* (U** - U*)
+  const R esg = lf ? -sg : sg;
+  R Fss[7];
+  Fss[0] = Fs[0];
+  Fss[1] = Fs[1];
+  Fss[2] = Fs[2] + Ss * rs * (w1 - vs1);
+  Fss[3] = Fs[3] + Ss * rs * (w2 - vs2);
+  Fss[4] = Fs[4] + Ss * sq * (vbs - vbss) * esg;
+  Fss[5] = Fs[5] + Ss * (c1 - bs1);
+  Fss[6] = Fs[6] + Ss * (c2 - bs2);
+  // region: outside the fan, single star, double star (eq. flux-hlld)
+  const bool outL = R(0) <= SL, outR = SR < R(0);
+  const bool star1 = lf ? (R(0) <= SsL) : (SsR < R(0));
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    R v = star1 ? Fs[c] : Fss[c];
+    v = outR ? qR.F[c] : v;
+    F[c] = outL ? qL.F[c] : v;
   }
 }
 

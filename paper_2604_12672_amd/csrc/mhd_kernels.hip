@@ -6,10 +6,13 @@
 // the three-cell reconstruction stencil, plus 64 ring cells two columns out
 // that only feed the x/y stencils).  The block marches up the segment; per
 // plane k it
-//   P1  converts plane k+2 to primitive deviations (EOS included) and
-//       reconstructs the z-faces of its own column (rolling registers),
-//   P2  solves the Riemann problems of the x- and y-faces of plane k+1 (cell
-//       plane staged in LDS) and of the z-face k+1/2,
+//   P1  converts plane k+2 to primitive deviations (EOS included) and stages
+//       it in LDS (two plane buffers), reconstructs cell k+1 of its own
+//       column along z and solves the z-face k+1/2, and reconstructs cell
+//       k+1 along x and y from the staged plane (one slope per cell and
+//       direction; the upper x value reaches the next lane by a shuffle,
+//       the upper y value goes through LDS),
+//   P2  solves the Riemann problems of the x- and y-faces of plane k+1,
 //   P3  updates the cells of plane k, accumulates the x/y flux divergence of
 //       plane k+1 and computes the Contact-CT edge EMFs E_z(k+1), E_x and
 //       E_y(k+1/2),
@@ -28,13 +31,28 @@
 
 namespace mhd {
 
-template <typename T>
-__device__ __forceinline__ T from_left(T v) {  // value of the lane at ci-1
-  return __shfl_up(v, 1, TT);
+// Row neighbours inside a 16-lane DPP row (one tile row): row_shr:1 reads
+// lane-1, row_shl:1 reads lane+1; the lane at the row edge gets 0 (its
+// result is never used).  Must be called with all lanes active.
+__device__ __forceinline__ int dpp_shr1(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x111, 0xf, 0xf, true);
 }
-template <typename T>
-__device__ __forceinline__ T from_right(T v) {  // value of the lane at ci+1
-  return __shfl_down(v, 1, TT);
+__device__ __forceinline__ int dpp_shl1(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x101, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(dpp_shr1(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(dpp_shl1(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = dpp_shr1(__double2loint(v)), hi = dpp_shr1(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = dpp_shl1(__double2loint(v)), hi = dpp_shl1(__double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
 // z plane q -> stored plane and mirror flag (reflecting walls)
@@ -104,34 +122,89 @@ __device__ __forceinline__ void prim_cell(const Phys &ph, const StagePtrs &p,
   }
 }
 
-// Face states of the sweep along `axis` from four consecutive cells m2..p1
-// (cells i-2, i-1, i, i+1 for the face i-1/2).
+// Number of reconstructed fields per face: rho, v_n, v_t1, v_t2, P, B_t1, B_t2
+// (+ gamma_e, gamma_c for the gas+radiation EOS).
+template <bool GR>
+struct NFS_ {
+  static constexpr int v = GR ? 9 : 7;
+};
+
+// Van Leer reconstruction of one cell along `axis` (0 x, 1 y, 2 z) from its
+// two neighbours: the cell's lower-face value lo (R state of face i-1/2) and
+// upper-face value hi (L state of face i+1/2), in the face frame of the
+// axis (n = axis, t1 = axis+1, t2 = axis+2).
 template <typename R, bool GR>
-__device__ __forceinline__ void face_states(int axis, const R *m2, const R *m1,
-                                            const R *c0, const R *p1,
-                                            Side<R> &L, Side<R> &Rt) {
-  // face frame: axis 0: n=x t1=y t2=z; 1: n=y t1=z t2=x; 2: n=z t1=x t2=y
+__device__ __forceinline__ void recon_cell(int axis, const R *m, const R *c,
+                                           const R *p, Side<R> &lo, Side<R> &hi) {
   const int vn = Q_VX + axis, v1 = Q_VX + (axis + 1) % 3, v2 = Q_VX + (axis + 2) % 3;
   const int b1 = Q_BX + (axis + 1) % 3, b2 = Q_BX + (axis + 2) % 3;
-  auto rec = [&](int f, R &l, R &r) {
-    const R sl = vanleer<R>(m1[f] - m2[f], c0[f] - m1[f]);
-    const R sr = vanleer<R>(c0[f] - m1[f], p1[f] - c0[f]);
-    l = m1[f] + R(0.5) * sl;
-    r = c0[f] - R(0.5) * sr;
+  auto rec = [&](int f, R &l, R &h) {
+    const R s = R(0.5) * vanleer<R>(c[f] - m[f], p[f] - c[f]);
+    l = c[f] - s;
+    h = c[f] + s;
   };
-  rec(Q_RHO, L.drho, Rt.drho);
-  rec(vn, L.vn, Rt.vn);
-  rec(v1, L.v1, Rt.v1);
-  rec(v2, L.v2, Rt.v2);
-  rec(Q_P, L.dp, Rt.dp);
-  rec(b1, L.b1, Rt.b1);
-  rec(b2, L.b2, Rt.b2);
+  rec(Q_RHO, lo.drho, hi.drho);
+  rec(vn, lo.vn, hi.vn);
+  rec(v1, lo.v1, hi.v1);
+  rec(v2, lo.v2, hi.v2);
+  rec(Q_P, lo.dp, hi.dp);
+  rec(b1, lo.b1, hi.b1);
+  rec(b2, lo.b2, hi.b2);
   if (GR) {
-    rec(Q_GE, L.dge, Rt.dge);
-    rec(Q_GC, L.dgc, Rt.dgc);
+    rec(Q_GE, lo.dge, hi.dge);
+    rec(Q_GC, lo.dgc, hi.dgc);
   } else {
-    L.dge = Rt.dge = L.dgc = Rt.dgc = R(0);
+    lo.dge = hi.dge = lo.dgc = hi.dgc = R(0);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ Side<R> side_from_left(const Side<R> &s) {
+  Side<R> o;
+  o.drho = from_left(s.drho);
+  o.vn = from_left(s.vn);
+  o.v1 = from_left(s.v1);
+  o.v2 = from_left(s.v2);
+  o.dp = from_left(s.dp);
+  o.b1 = from_left(s.b1);
+  o.b2 = from_left(s.b2);
+  o.dge = from_left(s.dge);
+  o.dgc = from_left(s.dgc);
+  return o;
+}
+
+template <typename R, bool GR>
+__device__ __forceinline__ void side_store(R (*buf)[NTHREADS], int t, const Side<R> &s) {
+  buf[0][t] = s.drho;
+  buf[1][t] = s.vn;
+  buf[2][t] = s.v1;
+  buf[3][t] = s.v2;
+  buf[4][t] = s.dp;
+  buf[5][t] = s.b1;
+  buf[6][t] = s.b2;
+  if (GR) {
+    buf[7][t] = s.dge;
+    buf[8][t] = s.dgc;
+  }
+}
+
+template <typename R, bool GR>
+__device__ __forceinline__ Side<R> side_load(R (*buf)[NTHREADS], int t) {
+  Side<R> s;
+  s.drho = buf[0][t];
+  s.vn = buf[1][t];
+  s.v1 = buf[2][t];
+  s.v2 = buf[3][t];
+  s.dp = buf[4][t];
+  s.b1 = buf[5][t];
+  s.b2 = buf[6][t];
+  if (GR) {
+    s.dge = buf[7][t];
+    s.dgc = buf[8][t];
+  } else {
+    s.dge = s.dgc = R(0);
+  }
+  return s;
 }
 
 // face flux -> conserved order (rho, m_x, m_y, m_z, E)
@@ -149,21 +222,37 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
     int zseg) {
   constexpr int NF = Cfg<R, GR>::NF;
+  constexpr int NS = NFS_<GR>::v;
   constexpr int LW = TT + 2;  // LDS plane edge: columns -2 .. 15
-  __shared__ R sW[NF][LW * LW];
-  __shared__ R sYF[5][NTHREADS];  // y-face conserved flux
-  __shared__ R sXE[2][NTHREADS];  // x-face E_z, mass flux
-  __shared__ R sZE[2][NTHREADS];  // z-face E_x, mass flux
-  __shared__ R sRX[2][NTHREADS];  // cell reference E_x, planes by parity
-  __shared__ R sRZ[NTHREADS];     // cell reference E_z of plane k+1
-  __shared__ R sEZ[2][NTHREADS];  // edge E_z, planes by parity
-  __shared__ R sEX[NTHREADS];     // edge E_x(k+1/2)
+  constexpr int LP = LW * LW;
+  __shared__ R sW[2][NF][LP];       // cell planes by parity
+  __shared__ R sYR[NS][NTHREADS];   // upper y-face states of plane k+1
+  __shared__ R sYF[5][NTHREADS];    // y-face conserved flux
+  __shared__ R sXE[2][NTHREADS];    // x-face E_z, mass flux
+  __shared__ R sZE[2][NTHREADS];    // z-face E_x, mass flux
+  __shared__ R sRX[2][NTHREADS];    // cell reference E_x, planes by parity
+  __shared__ R sRZ[NTHREADS];       // cell reference E_z of plane k+1
+  __shared__ R sEZ[2][NTHREADS];    // edge E_z, planes by parity
+  __shared__ R sEX[NTHREADS];       // edge E_x(k+1/2)
 
   const int tid = threadIdx.x;
   const int tx = tid % TT, ty = tid / TT;
   const int ci = tx - 1, cj = ty - 1;
-  const int X0 = blockIdx.x * TB, Y0 = blockIdx.y * TB;
-  const int z0 = blockIdx.z * zseg;
+  // Blocks are dealt round-robin to the 8 XCDs (separate L2 caches); remap
+  // so that each XCD works through a contiguous run of tiles (x fastest,
+  // then y, then z segment) and neighbouring tiles share its L2.
+  const int ntx = (ph.nx + TB - 1) / TB, nty = (ph.ny + TB - 1) / TB;
+  const int nblk = gridDim.x;
+  const int bid = blockIdx.x;
+  // XCD j receives the blocks bid = j, j+8, ...: ceil((nblk - j)/8) of them;
+  // they take the logical blocks [j q + min(j, r), ...) (q = nblk/8,
+  // r = nblk mod 8), a bijection onto [0, nblk)
+  const int q8 = nblk / 8, r8 = nblk % 8;
+  const int xcd = bid % 8, slot = bid / 8;
+  const int lb = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+  const int btx = lb % ntx, bty = (lb / ntx) % nty, bsz = lb / (ntx * nty);
+  const int X0 = btx * TB, Y0 = bty * TB;
+  const int z0 = bsz * zseg;
   const int z1 = min(z0 + zseg, ph.nz);
   const int gx = X0 + ci, gy = Y0 + cj;
   const int gi = wrapi(gx, ph.nx), gip = wrapi(gx + 1, ph.nx);
@@ -173,106 +262,154 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   const size_t ncell = plane * ph.nz;
   const size_t colq = (size_t)gj * ph.nx + gi;
 
-  // ring cells two columns outside the tile (x/y stencils only)
-  const bool ring = tid < 64;
+  // ring cells two columns outside the tile (x/y stencils only): the first
+  // 16 lanes of each wave take one of the four sides, so that every wave
+  // carries the same extra work into the first barrier
+  const int lane = tid & 63, wv = tid >> 6;
+  const bool ring = lane < 16;
   int rci = 0, rcj = 0;
-  if (tid < 16) {
-    rci = -2; rcj = tid - 1;
-  } else if (tid < 32) {
-    rci = TT - 1; rcj = tid - 17;
-  } else if (tid < 48) {
-    rci = tid - 33; rcj = -2;
+  if (wv == 0) {
+    rci = -2; rcj = lane - 1;
+  } else if (wv == 1) {
+    rci = TT - 1; rcj = lane - 1;
+  } else if (wv == 2) {
+    rci = lane - 1; rcj = -2;
   } else {
-    rci = tid - 49; rcj = TT - 1;
+    rci = lane - 1; rcj = TT - 1;
   }
   const int rgi = wrapi(X0 + rci, ph.nx), rgip = wrapi(X0 + rci + 1, ph.nx);
   const int rgj = wrapi(Y0 + rcj, ph.ny), rgjp = wrapi(Y0 + rcj + 1, ph.ny);
   const int lw_own = (cj + 2) * LW + (ci + 2);
   const int lw_ring = (rcj + 2) * LW + (rci + 2);
+  const int tdn = tid >= TT ? tid - TT : tid;            // (ci, cj-1)
+  const int tdl = tid >= TT + 1 ? tid - TT - 1 : tid;    // (ci-1, cj-1)
+  const int tup = tid + TT < NTHREADS ? tid + TT : tid;  // (ci, cj+1)
 
   const double dt = p.dt_dev ? *p.dt_dev : dt_host;
   const double cdt = cc * dt;
   const R gam = (R)ph.gamma, igm1 = (R)ph.igm1;
   const R mcut = (R)ph.mach_cut, imcut = (R)ph.imach_cut;
 
-  // rolling z-pipeline of the own column
-  R Wm[NF], Wc[NF], Wn[NF], Wr[NF];
-  Side<R> topk{}, topn{}, botn{};
-  // pipeline carries
-  R bxf_c = 0, byf_c = 0, bxf_n = 0, byf_n = 0;  // normal fields of plane k+1 / k+2
-  double acc[5] = {0, 0, 0, 0, 0};
-  R fzp[5] = {0, 0, 0, 0, 0};     // z-face conserved flux at k-1/2
-  R ex_prev = 0, ey_prev = 0;     // own edges E_x, E_y at k-1/2
-  R ez_cur = 0;                   // own edge E_z at plane k
+  // own column state carried along z
+  R Wc[NF];        // cell k+1
+  Side<R> topk{};  // upper z-face state of cell k (L state of face k+1/2)
+  R bxf_c = 0, byf_c = 0;  // normal fields on the lower x / y face, plane k+1
+  double acc[5] = {0, 0, 0, 0, 0};  // x/y flux divergence of plane k
+  R fzp[5] = {0, 0, 0, 0, 0};       // z-face conserved flux at k-1/2
+  R ex_prev = 0, ey_prev = 0;       // own edges E_x, E_y at k-1/2
+  R ez_cur = 0;                     // own edge E_z at plane k
   R xf_ey_prev = 0, xf_m_prev = 0;  // own x-face E_y and mass flux, plane k
   R yf_ex_prev = 0, yf_m_prev = 0;  // own y-face E_x and mass flux, plane k
   R rx_prev = 0, ry_prev = 0;       // own cell reference E_x, E_y, plane k
   unsigned long long nit = 0, nmax = 0, nfb = 0;
   int bad = 0;
 #pragma unroll
-  for (int f = 0; f < NF; ++f) Wm[f] = Wc[f] = Wn[f] = Wr[f] = R(0);
+  for (int f = 0; f < NF; ++f) Wc[f] = R(0);
 
   for (int k = z0 - 4; k < z1; ++k) {
-    // ---------------- P1: primitives of plane q = k+2 ------------------
+    // ---------------- P1 ------------------------------------------------
+    // primitives of plane k+2 (staged in LDS), z reconstruction of cell
+    // k+1 and the z-face k+1/2, x/y reconstruction of cell k+1
+    R Wn[NF];
+    R bxf_n, byf_n;
+    R fzc[5] = {0, 0, 0, 0, 0};
+    R zf_ey = 0, zf_ex = 0, zf_m = 0;
+    Side<R> xl{}, xll{}, yl{};
+    R rx = 0, ry = 0, rz = 0;
     {
       const int q = k + 2;
       int mir;
       const int kk = zsource(ph, q, mir);
-      CellLoad c;
-      load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
-      PrimOut o;
-      prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o);
-      bxf_n = (R)c.bxl;
-      byf_n = (R)c.byl;
-      if (GR) {
-        const bool own_cell = owner && q >= z0 && q < z1;
-        if (own_cell) {
-          p.Tout[(size_t)kk * plane + colq] = o.T;
-          nit += o.iters;
-          nmax = o.iters > nmax ? o.iters : nmax;
-          nfb += o.fallback;
-        }
-      }
-      bad |= o.bad;
-      if (ring) {
-        int rmir;
-        const int rkk = zsource(ph, q, rmir);
-        CellLoad rc;
-        load_cell(ph, p, rgi, rgip, rgj, rgjp, rkk, rmir, rc);
-        PrimOut ro;
-        prim_cell<R, GR>(ph, p, rc, rkk, rmir, Wr, ro);
-        bad |= ro.bad;
-      }
-      // reconstruct the own column along z at cell k+1
-      if (k >= z0 - 2) {
-        // slope of cell k+1 from (Wm = k, Wc = k+1, Wn = k+2): bottom (R
-        // state of face k+1/2) and top (L state of face k+3/2)
-        auto rz = [&](int f, R &bot, R &top) {
-          const R s = vanleer<R>(Wc[f] - Wm[f], Wn[f] - Wc[f]);
-          bot = Wc[f] - R(0.5) * s;
-          top = Wc[f] + R(0.5) * s;
-        };
-        rz(Q_RHO, botn.drho, topn.drho);
-        rz(Q_VZ, botn.vn, topn.vn);
-        rz(Q_VX, botn.v1, topn.v1);
-        rz(Q_VY, botn.v2, topn.v2);
-        rz(Q_P, botn.dp, topn.dp);
-        rz(Q_BX, botn.b1, topn.b1);
-        rz(Q_BY, botn.b2, topn.b2);
+      R *sWn = &sW[q & 1][0][0];
+      {
+        CellLoad c;
+        load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+        PrimOut o;
+        prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o);
+        bxf_n = (R)c.bxl;
+        byf_n = (R)c.byl;
         if (GR) {
-          rz(Q_GE, botn.dge, topn.dge);
-          rz(Q_GC, botn.dgc, topn.dgc);
-        } else {
-          botn.dge = topn.dge = botn.dgc = topn.dgc = R(0);
+          if (owner && q >= z0 && q < z1) {
+            p.Tout[(size_t)kk * plane + colq] = o.T;
+            nit += o.iters;
+            nmax = o.iters > nmax ? o.iters : nmax;
+            nfb += o.fallback;
+          }
         }
+        bad |= o.bad;
+      }
+      if (ring) {
+        CellLoad rc;
+        load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        PrimOut ro;
+        R Wr[NF];
+        prim_cell<R, GR>(ph, p, rc, kk, mir, Wr, ro);
+        bad |= ro.bad;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sWn[f * LP + lw_ring] = Wr[f];
+      }
+      // own cell k sits in the slot the new plane goes to; only this thread
+      // reads or writes that slot
+      R Wm[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        Wm[f] = sWn[f * LP + lw_own];
+        sWn[f * LP + lw_own] = Wn[f];
+      }
+      if (k >= z0 - 2) {
+        Side<R> botn, topn;
+        recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn);
+        if (k >= z0 - 1) {
+          const int fzi = zface(ph, k + 1);
+          FaceBg<R> bgf;
+          const int nzf = ph.nzf;
+          bgf.rho = (R)p.bg_fz[fzi];
+          bgf.p = (R)p.bg_fz[nzf + fzi];
+          bgf.ge = (R)p.bg_fz[2 * nzf + fzi];
+          bgf.gc = (R)p.bg_fz[3 * nzf + fzi];
+          const R bzn = (R)p.Bzs[(size_t)fzi * plane + colq];
+          R fz[7];
+          riemann<R, GR>(topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut, imcut, fz);
+          to_cons<R>(2, fz, fzc);
+          zf_ey = -fz[5];  // z-face E_y = -F_z[B_x]
+          zf_ex = fz[6];   // z-face E_x = +F_z[B_y]
+          zf_m = fz[0];
+        }
+        topk = topn;
+        // x/y reconstruction of cell k+1 from the staged plane k+1
+        const R *sWc = &sW[(k + 1) & 1][0][0];
+        // neighbours at ci-1 >= -2 and cj-1 >= -2 are staged (ring cells
+        // included): the halo column ci = -1 supplies the L state of the
+        // tile's first x-face
+        R a[NF], b[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          a[f] = sWc[f * LP + lw_own - 1];
+          b[f] = sWc[f * LP + lw_own + 1];
+        }
+        Side<R> xh;
+        recon_cell<R, GR>(0, a, Wc, b, xl, xh);
+        xll = side_from_left<R>(xh);  // L state of the x-face ci-1/2
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          a[f] = sWc[f * LP + lw_own - LW];
+          b[f] = sWc[f * LP + lw_own + LW];
+        }
+        Side<R> yh;
+        recon_cell<R, GR>(1, a, Wc, b, yl, yh);
+        side_store<R, GR>(sYR, tid, yh);
+        // cell reference EMF -(v x B) of plane k+1
+        rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);
+        ry = -(Wc[Q_VZ] * Wc[Q_BX] - Wc[Q_VX] * Wc[Q_BZ]);
+        rz = -(Wc[Q_VX] * Wc[Q_BY] - Wc[Q_VY] * Wc[Q_BX]);
       }
     }
+    __syncthreads();
 
-    // ---------------- P2: fluxes of plane k+1 and face k+1/2 -----------
-    R fx[7], fy[7], fz[7];
+    // ---------------- P2: x- and y-faces of plane k+1 --------------------
+    R fx[7], fy[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) fx[c] = fy[c] = fz[c] = R(0);
-    R rx = 0, ry = 0, rz_ = 0;
+    for (int c = 0; c < 7; ++c) fx[c] = fy[c] = R(0);
     if (k >= z0 - 2) {
       int mir;
       const int kc = zsource(ph, k + 1, mir);
@@ -281,85 +418,36 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       bgc.p = (R)p.bg_cc[ph.nz + kc];
       bgc.ge = (R)p.bg_cc[2 * ph.nz + kc];
       bgc.gc = (R)p.bg_cc[3 * ph.nz + kc];
-      // x-face ci-1/2 of row cj (stencil clamped inside the LDS plane)
-      {
-        const int i0 = ci - 2 < -2 ? -2 : ci - 2;
-        const int row = (cj + 2) * LW + 2;
-        R a0[NF], a1[NF], a2[NF], a3[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          a0[f] = sW[f][row + i0];
-          a1[f] = sW[f][row + i0 + 1];
-          a2[f] = sW[f][row + i0 + 2];
-          a3[f] = sW[f][row + i0 + 3];
-        }
-        Side<R> L, Rt;
-        face_states<R, GR>(0, a0, a1, a2, a3, L, Rt);
-        riemann<R, GR>(L, Rt, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
-      }
-      // y-face cj-1/2 of column ci
-      {
-        const int j0 = cj - 2 < -2 ? -2 : cj - 2;
-        const int col = ci + 2;
-        R a0[NF], a1[NF], a2[NF], a3[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          a0[f] = sW[f][(j0 + 2) * LW + col];
-          a1[f] = sW[f][(j0 + 3) * LW + col];
-          a2[f] = sW[f][(j0 + 4) * LW + col];
-          a3[f] = sW[f][(j0 + 5) * LW + col];
-        }
-        Side<R> L, Rt;
-        face_states<R, GR>(1, a0, a1, a2, a3, L, Rt);
-        riemann<R, GR>(L, Rt, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
-      }
-      // cell reference EMF -(v x B) of plane k+1 (own column)
-      rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);
-      ry = -(Wc[Q_VZ] * Wc[Q_BX] - Wc[Q_VX] * Wc[Q_BZ]);
-      rz_ = -(Wc[Q_VX] * Wc[Q_BY] - Wc[Q_VY] * Wc[Q_BX]);
-      if (k >= z0 - 1) {
-        // z-face k+1/2: L = top of cell k, R = bottom of cell k+1
-        const int fzi = zface(ph, k + 1);
-        FaceBg<R> bgf;
-        const int nzf = ph.nzf;
-        bgf.rho = (R)p.bg_fz[fzi];
-        bgf.p = (R)p.bg_fz[nzf + fzi];
-        bgf.ge = (R)p.bg_fz[2 * nzf + fzi];
-        bgf.gc = (R)p.bg_fz[3 * nzf + fzi];
-        const R bzn = (R)p.Bzs[(size_t)fzi * plane + colq];
-        riemann<R, GR>(topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut, imcut, fz);
-      }
+      riemann<R, GR>(xll, xl, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
+      const Side<R> yll = side_load<R, GR>(sYR, tdn);
+      riemann<R, GR>(yll, yl, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
       R fyc[5];
       to_cons<R>(1, fy, fyc);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sYF[f][tid] = fyc[f];
       sXE[0][tid] = -fx[5];  // x-face E_z = -F_x[B_y]
       sXE[1][tid] = fx[0];
-      sZE[0][tid] = fz[6];   // z-face E_x = +F_z[B_y]
-      sZE[1][tid] = fz[0];
+      sZE[0][tid] = zf_ex;
+      sZE[1][tid] = zf_m;
       sRX[(k + 1) & 1][tid] = rx;
-      sRZ[tid] = rz_;
+      sRZ[tid] = rz;
     }
     __syncthreads();
 
     // ---------------- P3: cells of plane k, divergence, edge EMFs -------
-    R fxc[5], fzc[5];
+    R fxc[5];
     to_cons<R>(0, fx, fxc);
-    to_cons<R>(2, fz, fzc);
     R fxr[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) fxr[f] = from_right(fxc[f]);
     // neighbour data at ci-1 (same row)
-    const R yf_ez_l = from_left(fy[6]);   // y-face E_z = +F_y[B_x]
+    const R yf_ez_l = from_left(fy[6]);  // y-face E_z = +F_y[B_x]
     const R yf_m_l = from_left(fy[0]);
-    const R rz_l = from_left(rz_);
-    const R zf_ey_l = from_left(-fz[5]);  // z-face E_y = -F_z[B_x]
-    const R zf_m_l = from_left(fz[0]);
+    const R rz_l = from_left(rz);
+    const R zf_ey_l = from_left(zf_ey);
+    const R zf_m_l = from_left(zf_m);
     const R ry_l = from_left(ry);
     const R ry_prev_l = from_left(ry_prev);
-    const int tdn = tid >= TT ? tid - TT : tid;            // (ci, cj-1)
-    const int tdl = tid >= TT + 1 ? tid - TT - 1 : tid;    // (ci-1, cj-1)
-    const int tup = tid + TT < NTHREADS ? tid + TT : tid;  // (ci, cj+1)
     R ex_new = 0, ey_new = 0, ez_new = 0;
     if (k >= z0 - 1) {
       // cells of plane k
@@ -394,40 +482,31 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         }
       }
       // x/y divergence of plane k+1
-      R fyu[5];
-#pragma unroll
-      for (int f = 0; f < 5; ++f) fyu[f] = sYF[f][tup];
       R fyc[5];
       to_cons<R>(1, fy, fyc);
 #pragma unroll
       for (int f = 0; f < 5; ++f)
         acc[f] = ((double)fxr[f] - (double)fxc[f]) * ph.idx +
-                 ((double)fyu[f] - (double)fyc[f]) * ph.idy;
-      // E_z at (ci-1/2, cj-1/2, k+1)
-      ez_new = ct_edge<R>(-fx[5], sXE[0][tdn], fy[6], yf_ez_l, rz_, rz_l, sRZ[tdn],
+                 ((double)sYF[f][tup] - (double)fyc[f]) * ph.idy;
+      // E_z at (ci-1/2, cj-1/2, k+1): a = x, b = y
+      ez_new = ct_edge<R>(-fx[5], sXE[0][tdn], fy[6], yf_ez_l, rz, rz_l, sRZ[tdn],
                           sRZ[tdl], fx[0], sXE[1][tdn], fy[0], yf_m_l);
       // E_x at (ci, cj-1/2, k+1/2): a = y (y-faces at planes k+1, k),
       // b = z (z-faces at cj, cj-1)
       const int s1 = (k + 1) & 1, s0 = k & 1;
-      ex_new = ct_edge<R>(-fy[5], yf_ex_prev, fz[6], sZE[0][tdn], rx, sRX[s1][tdn], rx_prev,
-                          sRX[s0][tdn], fy[0], yf_m_prev, fz[0], sZE[1][tdn]);
+      ex_new = ct_edge<R>(-fy[5], yf_ex_prev, zf_ex, sZE[0][tdn], rx, sRX[s1][tdn], rx_prev,
+                          sRX[s0][tdn], fy[0], yf_m_prev, zf_m, sZE[1][tdn]);
       // E_y at (ci-1/2, cj, k+1/2): a = z (z-faces at ci, ci-1), b = x
       // (x-faces at planes k+1, k)
-      ey_new = ct_edge<R>(-fz[5], zf_ey_l, fx[6], xf_ey_prev, ry, ry_prev, ry_l, ry_prev_l,
-                          fz[0], zf_m_l, fx[0], xf_m_prev);
+      ey_new = ct_edge<R>(zf_ey, zf_ey_l, fx[6], xf_ey_prev, ry, ry_prev, ry_l, ry_prev_l,
+                          zf_m, zf_m_l, fx[0], xf_m_prev);
+      // a reflecting wall carries no tangential EMF
       if (ph.reflect && (k + 1 == 0 || k + 1 == ph.nz)) {
         ex_new = R(0);
         ey_new = R(0);
       }
       sEZ[(k + 1) & 1][tid] = ez_new;
       sEX[tid] = ex_new;
-    }
-    // stage the cell plane k+2 for the next x/y sweep
-#pragma unroll
-    for (int f = 0; f < NF; ++f) sW[f][lw_own] = Wn[f];
-    if (ring) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f) sW[f][lw_ring] = Wr[f];
     }
     __syncthreads();
 
@@ -472,12 +551,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     yf_m_prev = fy[0];
     rx_prev = rx;
     ry_prev = ry;
-    topk = topn;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      Wm[f] = Wc[f];
-      Wc[f] = Wn[f];
-    }
+    for (int f = 0; f < NF; ++f) Wc[f] = Wn[f];
     bxf_c = bxf_n;
     byf_c = byf_n;
   }
@@ -515,7 +590,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
 hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
                         double cc, double dt_host) {
   const Phys &ph = c.ph;
-  dim3 grid((ph.nx + TB - 1) / TB, (ph.ny + TB - 1) / TB, (ph.nz + c.zseg - 1) / c.zseg);
+  const int nblk = ((ph.nx + TB - 1) / TB) * ((ph.ny + TB - 1) / TB) * ((ph.nz + c.zseg - 1) / c.zseg);
+  dim3 grid(nblk);
   dim3 block(NTHREADS);
   const bool gr = ph.gasrad != 0;
   const bool split = c.d.precision == MHD_PREC_SPLIT;
