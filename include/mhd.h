@@ -129,6 +129,30 @@ int mhd_set_background(mhd_ctx *ctx, const double *w_cc, const double *w_fz);
 int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *force,
                     int32_t where);
 
+/* Learned initial guess of the Newton temperature inversion (contexts
+   created with MHD_GUESS_MLP; not part of the paper's method).  Network
+   2 -> 64 -> 64 -> 1 with ReLU: h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2),
+   y = W3 h2 + b3, with x = ((log10 rho - norm[0]) norm[1],
+   (log10 e_int - norm[2]) norm[3]) clipped to [-1, 1] and the guess
+   T0 = 10^(y / norm[5] + norm[4]).  Host arrays: w1 [64][2] and b1 [64]
+   FP32, w2 [64 out][64 in] and w3 [64] BF16 bit patterns, b2 [64] FP32, b3,
+   norm [6].  All three layers run on the matrix cores with FP32
+   accumulation; Newton then polishes in FP64 (at most 8 steps, then the
+   bracketed solve).  Must precede the first step.  Copies the weights. */
+int mhd_set_eos_mlp(mhd_ctx *ctx, const float *w1, const float *b1,
+                    const uint16_t *w2, const float *b2, const uint16_t *w3,
+                    float b3, const double *norm);
+
+/* Batch temperature inversion on device arrays (gas+radiation only): T[i]
+   solves e_int(rho[i], T) = e[i] (Sect. 2.2) from the context's guess mode
+   (MHD_GUESS_PREV_T: T_guess[i], or the bracketed solve when T_guess is
+   NULL; MHD_GUESS_MLP: the learned guess).  T0 (nullable) receives the
+   guess used.  stats (nullable) = {Newton steps, largest count, bracketed
+   solves}.  All pointers are device memory; synchronises. */
+int mhd_eos_solve(mhd_ctx *ctx, const double *rho, const double *e,
+                  const double *T_guess, int64_t n, double *T, double *T0,
+                  int64_t stats[3]);
+
 /* Load the state.  T (nullable) is the initial temperature guess for
    MHD_GUESS_PREV_T; when NULL the library solves T with the bracketed
    method.  The wall planes of Bz are forced to zero for a reflecting z. */
@@ -149,8 +173,9 @@ int mhd_step(mhd_ctx *ctx, double dt);
    round trip).  Equivalent to nsteps x (mhd_compute_dt; mhd_step). */
 int mhd_advance(mhd_ctx *ctx, double cfl, int32_t nsteps);
 
-/* Copy the state out (synchronises).  T (nullable) receives the current
-   temperature (gas+radiation only). */
+/* Copy the state out (synchronises).  T (nullable) receives the
+   temperature of the current state (gas+radiation only), solved on demand;
+   the guess kept for the next step is not changed. */
 int mhd_get_state(mhd_ctx *ctx, double *U, double *Bx, double *By, double *Bz,
                   double *T, int32_t where);
 

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "mhd_internal.h"
 
@@ -104,8 +105,8 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "unknown eos_guess";
     return MHD_ERR_ARG;
   }
-  if (d->eos_guess == MHD_GUESS_MLP) {
-    msg = "the learned EOS guess is not available in this build";
+  if (d->eos_guess == MHD_GUESS_MLP && d->eos != MHD_EOS_GASRAD) {
+    msg = "the learned guess needs the gas+radiation EOS";
     return MHD_ERR_ARG;
   }
   if (d->xi_mode < MHD_XI_LINEAR || d->xi_mode > MHD_XI_OFF) {
@@ -197,6 +198,8 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   ph.dims_active[0] = desc->nx > 1;
   ph.dims_active[1] = desc->ny > 1;
   ph.dims_active[2] = desc->nz > 1;
+  // after the learned guess Newton gets 8 steps before the bracketed solve
+  ph.newton_maxit_mlp = desc->newton_maxit < 8 ? desc->newton_maxit : 8;
   c.ncell = (size_t)desc->nx * desc->ny * desc->nz;
   c.nfz = (size_t)desc->nx * desc->ny * ph.nzf;
   // z planes per stage block: a longer segment re-reads fewer halo planes
@@ -229,6 +232,8 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
     if ((e = hipMemsetAsync(c.Bz[s], 0, sizeof(double) * c.nfz, c.stream)) != hipSuccess)
       return cleanup(e, "hipMemset Bz");
   }
+  if (desc->eos_guess == MHD_GUESS_MLP)
+    if ((e = hipMalloc(&c.mlp, mhd::mlp_bytes())) != hipSuccess) return cleanup(e, "hipMalloc mlp");
   if (ph.gasrad)
     for (int s = 0; s < 2; ++s)
       if ((e = hipMalloc(&c.T[s], sizeof(double) * c.ncell)) != hipSuccess)
@@ -278,6 +283,7 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.dt_dev);
   (void)hipFree(c.flags);
   (void)hipFree(c.nstats);
+  (void)hipFree(c.mlp);
   delete h;
   return MHD_OK;
 }
@@ -341,11 +347,12 @@ int mhd_set_state(mhd_ctx *h, const double *U, const double *Bx, const double *B
   HIPCHK(h, hipMemcpyAsync(c.Bz[s], Bz, sizeof(double) * c.nfz, kind_in(where), c.stream));
   if (c.ph.reflect) HIPCHK(h, mhd::launch_zero_walls(c, c.Bz[s]));
   HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
-  if (c.ph.gasrad) {
+  if (c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T) {
     if (T)
       HIPCHK(h, hipMemcpyAsync(c.T[c.tcur], T, sizeof(double) * c.ncell, kind_in(where), c.stream));
     else
-      HIPCHK(h, mhd::launch_init_temperature(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[c.tcur]));
+      HIPCHK(h, mhd::launch_init_temperature(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], nullptr,
+                                             c.T[c.tcur]));
   }
   c.have_state = true;
   return latched(h);
@@ -353,6 +360,8 @@ int mhd_set_state(mhd_ctx *h, const double *U, const double *Bx, const double *B
 
 static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
   mhd::Ctx &c = h->c;
+  if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
+    return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   const int ns = c.d.rk_order == 3 ? 3 : 2;
   const double(*co)[3] = c.d.rk_order == 3 ? kRK3 : kRK2;
   const int n = c.cur;
@@ -377,8 +386,10 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.Bxo = c.Bx[o];
     p.Byo = c.By[o];
     p.Bzo = c.Bz[o];
-    p.Tin = c.ph.gasrad ? c.T[c.tcur] : nullptr;
-    p.Tout = c.ph.gasrad ? c.T[1 - c.tcur] : nullptr;
+    const bool prev_t = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T;
+    p.Tin = prev_t ? c.T[c.tcur] : nullptr;
+    p.Tout = prev_t ? c.T[1 - c.tcur] : nullptr;
+    p.mlp = c.mlp;
     p.bg_cc = c.bg_cc;
     p.bg_fz = c.bg_fz;
     p.heat = c.heat;
@@ -387,7 +398,7 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.flags = c.flags;
     p.newton_stats = c.nstats;
     HIPCHK(h, mhd::launch_stage(c, p, co[s][0], co[s][1], co[s][2], dt_host));
-    if (c.ph.gasrad) c.tcur = 1 - c.tcur;
+    if (prev_t) c.tcur = 1 - c.tcur;
     in = o;
   }
   c.cur = in;
@@ -407,6 +418,8 @@ int mhd_advance(mhd_ctx *h, double cfl, int32_t nsteps) {
   if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_advance before mhd_set_state");
   if (!(cfl > 0.0) || !std::isfinite(cfl) || nsteps < 0)
     return fail(h, MHD_ERR_ARG, "cfl must be > 0 and nsteps >= 0");
+  if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
+    return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   for (int s = 0; s < nsteps; ++s) {
     const int n = c.cur;
     HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
@@ -422,6 +435,8 @@ int mhd_compute_dt(mhd_ctx *h, double cfl, double *dt_out) {
   mhd::Ctx &c = h->c;
   if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_compute_dt before mhd_set_state");
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, MHD_ERR_ARG, "cfl must be > 0");
+  if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
+    return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   const int n = c.cur;
   HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
                                      c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev));
@@ -448,7 +463,14 @@ int mhd_get_state(mhd_ctx *h, double *U, double *Bx, double *By, double *Bz, dou
   if (Bz) HIPCHK(h, hipMemcpyAsync(Bz, c.Bz[s], sizeof(double) * c.nfz, kind_out(where), c.stream));
   if (T) {
     if (!c.ph.gasrad) return fail(h, MHD_ERR_ARG, "T requested for the ideal-gas EOS");
-    HIPCHK(h, hipMemcpyAsync(T, c.T[c.tcur], sizeof(double) * c.ncell, kind_out(where), c.stream));
+    // temperature of the current state: Newton from the stored solution of
+    // the last stage (previous-T mode, which keeps its guess array), or
+    // the bracketed solve (learned mode stores no temperature)
+    const bool prev_t = c.d.eos_guess == MHD_GUESS_PREV_T;
+    double *dst = prev_t ? c.T[1 - c.tcur] : c.T[0];
+    HIPCHK(h, mhd::launch_init_temperature(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s],
+                                           prev_t ? c.T[c.tcur] : nullptr, dst));
+    HIPCHK(h, hipMemcpyAsync(T, dst, sizeof(double) * c.ncell, kind_out(where), c.stream));
   }
   return latched(h);
 }
@@ -481,6 +503,93 @@ int mhd_diagnostics(mhd_ctx *h, mhd_diag *out) {
   out->newton_max = (int64_t)st[1];
   out->fallbacks = (int64_t)st[2];
   out->error_flags = flags;
+  return latched(h);
+}
+
+int mhd_set_eos_mlp(mhd_ctx *h, const float *w1, const float *b1, const uint16_t *w2,
+                    const float *b2, const uint16_t *w3, float b3, const double *norm) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (c.d.eos_guess != MHD_GUESS_MLP)
+    return fail(h, MHD_ERR_STATE, "context was not created with MHD_GUESS_MLP");
+  if (!w1 || !b1 || !w2 || !b2 || !w3 || !norm)
+    return fail(h, MHD_ERR_ARG, "network arrays must not be NULL");
+  auto finite_f = [](const float *a, int n) {
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(a[i])) return false;
+    return true;
+  };
+  if (!finite_f(w1, 128) || !finite_f(b1, 64) || !finite_f(b2, 64) || !std::isfinite(b3))
+    return fail(h, MHD_ERR_ARG, "network weights must be finite");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(norm[i])) return fail(h, MHD_ERR_ARG, "normalisation must be finite");
+  if (norm[1] == 0.0 || norm[3] == 0.0 || norm[5] == 0.0)
+    return fail(h, MHD_ERR_ARG, "normalisation scales must be nonzero");
+  // pack the fragments in the lane order of the kernel (see MlpLds)
+  std::vector<unsigned char> buf(mhd::mlp_bytes(), 0);
+  auto bf = [](float x) -> uint16_t {  // round to nearest even
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  };
+  auto bfv = [](uint16_t b) -> float {
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+  };
+  uint16_t *a1 = (uint16_t *)buf.data();  // [2][64][4]
+  uint16_t *a2 = a1 + 2 * 64 * 4;          // [2][8][64][4]
+  float *c2 = (float *)(a2 + 2 * 8 * 64 * 4);  // [2][16][64]
+  uint16_t *w3b = (uint16_t *)(c2 + 2 * 16 * 64);  // [64]
+  for (int mb = 0; mb < 2; ++mb)
+    for (int l = 0; l < 64; ++l) {
+      const int m = 32 * mb + (l % 32);
+      const float w0 = w1[2 * m], wv1 = w1[2 * m + 1], bb = b1[m];
+      const uint16_t w0h = bf(w0), w1h = bf(wv1), bh = bf(bb);
+      const uint16_t w0l = bf(w0 - bfv(w0h)), w1l = bf(wv1 - bfv(w1h)), bl = bf(bb - bfv(bh));
+      uint16_t *d = a1 + (mb * 64 + l) * 4;
+      if (l < 32) {
+        d[0] = w0h; d[1] = w0l; d[2] = w0h; d[3] = w1h;
+      } else {
+        d[0] = w1l; d[1] = w1h; d[2] = bh; d[3] = bl;
+      }
+      for (int kb = 0; kb < 8; ++kb)
+        for (int t = 0; t < 4; ++t)
+          a2[((mb * 8 + kb) * 64 + l) * 4 + t] = w2[m * 64 + 8 * kb + 4 * (l / 32) + t];
+      for (int r = 0; r < 16; ++r)
+        c2[(mb * 16 + r) * 64 + l] = b2[32 * mb + 8 * (r / 4) + 4 * (l / 32) + r % 4];
+    }
+  for (int i = 0; i < 64; ++i) w3b[i] = w3[i];
+  HIPCHK(h, hipMemcpyAsync(c.mlp, buf.data(), buf.size(), hipMemcpyHostToDevice, c.stream));
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  for (int i = 0; i < 6; ++i) c.ph.mlp_norm[i] = (float)norm[i];
+  c.ph.mlp_b3 = b3;
+  c.ph.mlp_inv_sT = (float)(1.0 / norm[5]);
+  c.have_mlp = true;
+  return MHD_OK;
+}
+
+int mhd_eos_solve(mhd_ctx *h, const double *rho, const double *e, const double *T_guess,
+                  int64_t n, double *T, double *T0, int64_t stats[3]) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.ph.gasrad) return fail(h, MHD_ERR_ARG, "mhd_eos_solve needs the gas+radiation EOS");
+  if (!rho || !e || !T || n < 0) return fail(h, MHD_ERR_ARG, "bad arguments");
+  if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
+    return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
+  if (n == 0) return MHD_OK;
+  HIPCHK(h, hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream));
+  HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
+  HIPCHK(h, mhd::launch_eos_solve(c, rho, e, c.d.eos_guess == MHD_GUESS_MLP ? nullptr : T_guess,
+                                  (long long)n, T, T0));
+  if (stats) {
+    unsigned long long st[3];
+    HIPCHK(h, hipMemcpyAsync(st, c.nstats, sizeof(st), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(h, hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 3; ++i) stats[i] = (int64_t)st[i];
+  }
   return latched(h);
 }
 

@@ -62,7 +62,7 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 // [min(e/(2C_g), (rho e/(2a))^1/4), min(e/C_g, (rho e/a)^1/4)].
 // Returns 0, or 2 when even the bracketed solve did not converge.
 __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
-                                               double e, double tguess,
+                                               double e, double tguess, int maxit,
                                                double &T, int &iters,
                                                int &fallback) {
   const double cg = ph.cg, ar = ph.arad / rho, tol = ph.newton_tol * e;
@@ -70,7 +70,7 @@ __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
   fallback = 0;
   double t = tguess;
   if (t > 0.0 && t < INFINITY) {
-    for (int n = 0; n < ph.newton_maxit; ++n) {
+    for (int n = 0; n < maxit; ++n) {
       const double t3 = t * t * t;
       const double de = e - (cg * t + ar * t3 * t);
       if (fabs(de) < tol) {
@@ -137,17 +137,26 @@ struct PrimOut {
   int bad;       // 1 unphysical, 2 EOS failure
 };
 
+// specific internal energy e_int = (E - rho v^2/2 - B_cc^2/2) / rho
+__device__ __forceinline__ double specific_eint(const double u[5], const double b[3]) {
+  const double rho = u[0];
+  const double ir = 1.0 / rho;
+  const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+  const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  return (u[4] - 0.5 * rho * (vx * vx + vy * vy + vz * vz) - 0.5 * b2) * ir;
+}
+
 // u: conserved (rho, m, E); b: cell-centred field; bg: background
 // (rho, P, gamma_e, gamma_c) of the cell's height.
 template <bool GR>
 __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
                                           const double b[3], double tguess,
-                                          const double bg[4], PrimOut &o) {
+                                          const double bg[4], PrimOut &o,
+                                          int maxit = -1) {
   const double rho = u[0];
   const double ir = 1.0 / rho;
   const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-  const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-  const double e = (u[4] - 0.5 * rho * (vx * vx + vy * vy + vz * vz) - 0.5 * b2) * ir;
+  const double e = specific_eint(u, b);
   o.bad = (rho > 0.0 && e > 0.0 && e < INFINITY) ? 0 : 1;
   double P, ge = ph.gamma, gc = ph.gamma;
   o.T = 0.0;
@@ -156,7 +165,9 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
   if (GR) {
     double T = tguess;
     if (!o.bad) {
-      if (eos_temperature(ph, rho, e, tguess, T, o.iters, o.fallback)) o.bad = 2;
+      if (eos_temperature(ph, rho, e, tguess, maxit < 0 ? ph.newton_maxit : maxit, T, o.iters,
+                          o.fallback))
+        o.bad = 2;
     }
     o.T = T;
     eos_thermo(ph, rho, e, T, P, ge, gc);
@@ -173,6 +184,134 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
   o.w[Q_BZ] = b[2];
   o.w[Q_GE] = ge - bg[2];
   o.w[Q_GC] = gc - bg[3];
+}
+
+// ---------------------------------------------------------------------------
+// learned initial guess of T(rho, e_int) on the matrix cores
+//
+// A 2 -> 64 -> 64 -> 1 ReLU network evaluated for 32 cells per pass with
+// v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32, FP32 accumulation).
+// Operand layout (lane l, t = 0..3, r = 0..15):
+//   A: A[l%32][4(l/32) + t]     B: B[4(l/32) + t][l%32]
+//   D: row 8(r/4) + 4(l/32) + r%4, column l%32
+// so the accumulator of one layer, taken four registers at a time, is the B
+// operand of the next (rows = hidden units, columns = cells).  Layer 1 folds
+// its bias into K = 8 rows (x0h, x0h, x0l, x1h | x1h, x1l, 1, 1) against
+// (w0h, w0l, w0h, w1h | w1l, w1h, b1h, b1l): hi/lo BF16 pairs keep about 16
+// bits of the inputs and of W1, b1.  Layer 3 is a 32-row MFMA whose row 0
+// is W3.
+// ---------------------------------------------------------------------------
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+struct MlpLds {        // host-packed fragments, staged in LDS per block
+  v4s a1[2][64];       // layer 1, per output block mb and lane
+  v4s a2[2][8][64];    // layer 2: W2[32mb + l%32][8kb + 4(l/32) + t]
+  float c2[2][16][64]; // layer-2 accumulator start: b2 in the D layout
+  short w3[64];        // layer 3 weights (BF16 bits)
+};
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  return __builtin_bit_cast(short, (__bf16)x);
+}
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
+__device__ __forceinline__ v4s pack_bf16(float a, float b, float c, float d) {
+  v4s r;
+  r[0] = bf16_bits(a);
+  r[1] = bf16_bits(b);
+  r[2] = bf16_bits(c);
+  r[3] = bf16_bits(d);
+  return r;
+}
+
+// One pass over the 32 cells held by lanes 0..31 (lanes l and l+32 carry
+// the inputs of cell l%32).  Returns the network output on lanes 0..31.
+// Must be called by all 64 lanes.
+__device__ __forceinline__ float mlp_pass(const MlpLds &S, float x0, float x1, int lane) {
+  const float x0h = bf16_round(x0), x1h = bf16_round(x1);
+  const v4s b = lane < 32 ? pack_bf16(x0h, x0h, x0 - x0h, x1h)
+                          : pack_bf16(x1h, x1 - x1h, 1.0f, 1.0f);
+  const v16f z = {};
+  const v16f c0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a1[0][lane], b, z, 0, 0, 0);
+  const v16f c1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a1[1][lane], b, z, 0, 0, 0);
+  v4s h[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h[j] = pack_bf16(fmaxf(c0[4 * j], 0.f), fmaxf(c0[4 * j + 1], 0.f), fmaxf(c0[4 * j + 2], 0.f),
+                     fmaxf(c0[4 * j + 3], 0.f));
+    h[4 + j] = pack_bf16(fmaxf(c1[4 * j], 0.f), fmaxf(c1[4 * j + 1], 0.f),
+                         fmaxf(c1[4 * j + 2], 0.f), fmaxf(c1[4 * j + 3], 0.f));
+  }
+  v16f d0, d1;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    d0[r] = S.c2[0][r][lane];
+    d1[r] = S.c2[1][r][lane];
+  }
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    d0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[0][kb][lane], h[kb], d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[1][kb][lane], h[kb], d1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h[j] = pack_bf16(fmaxf(d0[4 * j], 0.f), fmaxf(d0[4 * j + 1], 0.f), fmaxf(d0[4 * j + 2], 0.f),
+                     fmaxf(d0[4 * j + 3], 0.f));
+    h[4 + j] = pack_bf16(fmaxf(d1[4 * j], 0.f), fmaxf(d1[4 * j + 1], 0.f),
+                         fmaxf(d1[4 * j + 2], 0.f), fmaxf(d1[4 * j + 3], 0.f));
+  }
+  v16f e = {};
+  const bool col0 = (lane & 31) == 0;
+  const int kh = 4 * (lane >> 5);
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    v4s a;
+    a[0] = col0 ? S.w3[8 * kb + kh] : (short)0;
+    a[1] = col0 ? S.w3[8 * kb + kh + 1] : (short)0;
+    a[2] = col0 ? S.w3[8 * kb + kh + 2] : (short)0;
+    a[3] = col0 ? S.w3[8 * kb + kh + 3] : (short)0;
+    e = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, h[kb], e, 0, 0, 0);
+  }
+  return e[0];
+}
+
+// Network inputs of one cell: normalised log10 rho and log10 e, clipped to
+// the training box [-1, 1].
+__device__ __forceinline__ void mlp_inputs(const Phys &ph, double rho, double e, float &x0,
+                                           float &x1) {
+  const float l2 = 0.30102999566398120f;  // log10(2)
+  x0 = (__log2f((float)rho) * l2 - ph.mlp_norm[0]) * ph.mlp_norm[1];
+  x1 = (__log2f((float)e) * l2 - ph.mlp_norm[2]) * ph.mlp_norm[3];
+  x0 = fminf(fmaxf(x0, -1.0f), 1.0f);
+  x1 = fminf(fmaxf(x1, -1.0f), 1.0f);
+  if (!(x0 == x0)) x0 = 0.0f;  // NaN inputs of non-physical cells
+  if (!(x1 == x1)) x1 = 0.0f;
+}
+
+// Temperature guess from the network output y: log10 T = (y + b3)/s_T + c_T.
+__device__ __forceinline__ double mlp_temperature(const Phys &ph, float y) {
+  const float lg = (y + ph.mlp_b3) * ph.mlp_inv_sT + ph.mlp_norm[4];
+  return (double)exp2f(lg * 3.32192809488736235f);
+}
+
+// Guess for the cells held by all 64 lanes of the wave (two passes).
+__device__ __forceinline__ double mlp_guess_wave(const Phys &ph, const MlpLds &S, float x0,
+                                                 float x1, int lane) {
+  const float o0 = __shfl_xor(x0, 32), o1 = __shfl_xor(x1, 32);
+  const bool lo = lane < 32;
+  const float y0 = mlp_pass(S, lo ? x0 : o0, lo ? x1 : o1, lane);  // cells 0..31
+  const float y1 = mlp_pass(S, lo ? o0 : x0, lo ? o1 : x1, lane);  // cells 32..63
+  const float y1x = __shfl_xor(y1, 32);
+  return mlp_temperature(ph, lo ? y0 : y1x);
+}
+
+// Guess for the cells held by lanes 0..31 only (one pass).
+__device__ __forceinline__ double mlp_guess_low(const Phys &ph, const MlpLds &S, float x0,
+                                                float x1, int lane) {
+  const float o0 = __shfl_xor(x0, 32), o1 = __shfl_xor(x1, 32);
+  const bool lo = lane < 32;
+  return mlp_temperature(ph, mlp_pass(S, lo ? x0 : o0, lo ? x1 : o1, lane));
 }
 
 // ---------------------------------------------------------------------------

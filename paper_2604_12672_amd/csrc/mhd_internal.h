@@ -31,6 +31,9 @@ struct Phys {
   int xi_mode;
   double mach_cut, imach_cut;
   int dims_active[3];  // axis has more than one cell
+  int newton_maxit_mlp;  // Newton cap after the learned guess
+  float mlp_norm[6];     // c_rho, s_rho, c_e, s_e, c_T, s_T
+  float mlp_b3, mlp_inv_sT;
 };
 
 // Pointers of one stage launch.
@@ -43,6 +46,7 @@ struct StagePtrs {
   const double *bg_cc, *bg_fz;         // [4][nz], [4][nzf]
   const double *heat, *force;          // nullable
   const double *dt_dev;                // device dt (nullable: use dt_host)
+  const void *mlp;                     // packed guess network (MlpLds layout)
   int *flags;                          // latched error flags
   unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
 };
@@ -64,6 +68,8 @@ struct Ctx {
   double *bg_cc = nullptr, *bg_fz = nullptr;
   double *heat = nullptr, *force = nullptr;
   double *dt_dev = nullptr;       // [1]
+  void *mlp = nullptr;            // packed guess network on the device
+  bool have_mlp = false;
   double *red = nullptr;          // reduction scratch
   size_t red_len = 0;
   int *flags = nullptr;           // [1]
@@ -81,10 +87,13 @@ hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
                                const double *T, double cfl, double *dt_dev);
 hipError_t launch_init_temperature(const Ctx &c, const double *U,
                                    const double *Bx, const double *By,
-                                   const double *Bz, double *T);
+                                   const double *Bz, const double *Tg, double *T);
 hipError_t launch_diagnostics(const Ctx &c, const double *U, const double *Bx,
                               const double *By, const double *Bz,
                               double *out /* host, 12 */);
 hipError_t launch_zero_walls(const Ctx &c, double *Bz);
+size_t mlp_bytes();
+hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
+                            const double *tguess, long long n, double *T, double *T0);
 
 }  // namespace mhd

@@ -106,13 +106,13 @@ struct Cfg {
 template <typename R, bool GR>
 __device__ __forceinline__ void prim_cell(const Phys &ph, const StagePtrs &p,
                                           const CellLoad &c, int kk, int mirror,
-                                          R *w, PrimOut &o) {
+                                          R *w, PrimOut &o, int maxit = -1) {
   double bg[4];
   bg[0] = p.bg_cc[kk];
   bg[1] = p.bg_cc[ph.nz + kk];
   bg[2] = p.bg_cc[2 * ph.nz + kk];
   bg[3] = p.bg_cc[3 * ph.nz + kk];
-  cons2prim<GR>(ph, c.u, c.b, c.tg, bg, o);
+  cons2prim<GR>(ph, c.u, c.b, c.tg, bg, o, maxit);
   constexpr int NF = Cfg<R, GR>::NF;
 #pragma unroll
   for (int f = 0; f < NF; ++f) w[f] = (R)o.w[f];
@@ -217,11 +217,26 @@ __device__ __forceinline__ void to_cons(int axis, const R F[7], R out[5]) {
   out[4] = F[4];
 }
 
-template <typename R, bool GR>
+// Copy the packed guess network into LDS (all threads; caller syncs).
+__device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, int nthreads) {
+  const uint4 *s4 = (const uint4 *)src;
+  uint4 *d4 = (uint4 *)dst;
+  for (int i = tid; i < (int)(sizeof(MlpLds) / 16); i += nthreads) d4[i] = s4[i];
+}
+
+template <typename R, bool GR, bool ML>
 __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
     int zseg) {
+  static_assert(!ML || GR, "the learned guess belongs to the gas+radiation EOS");
+  static_assert(sizeof(MlpLds) % 16 == 0, "MlpLds is copied in 16-byte words");
   constexpr int NF = Cfg<R, GR>::NF;
+  __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
+  const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
+  if (ML) {
+    stage_mlp(p.mlp, sMlpRaw, threadIdx.x, NTHREADS);
+    __syncthreads();
+  }
   constexpr int NS = NFS_<GR>::v;
   constexpr int LW = TT + 2;  // LDS plane edge: columns -2 .. 15
   constexpr int LP = LW * LW;
@@ -321,16 +336,28 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       int mir;
       const int kk = zsource(ph, q, mir);
       R *sWn = &sW[q & 1][0][0];
+      CellLoad c, rc;
+      load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+      if (ML) {
+        if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        // learned guesses for the own cells (two passes) and for the ring
+        // cells of lanes 0..15 (one pass); every lane takes part
+        float x0, x1, r0 = 0.0f, r1 = 0.0f;
+        mlp_inputs(ph, c.u[0], specific_eint(c.u, c.b), x0, x1);
+        if (ring) mlp_inputs(ph, rc.u[0], specific_eint(rc.u, rc.b), r0, r1);
+        c.tg = mlp_guess_wave(ph, sMlp, x0, x1, lane);
+        const double tr = mlp_guess_low(ph, sMlp, r0, r1, lane);
+        rc.tg = tr;
+      }
+      const int maxit = ML ? ph.newton_maxit_mlp : ph.newton_maxit;
       {
-        CellLoad c;
-        load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
         PrimOut o;
-        prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o);
+        prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o, maxit);
         bxf_n = (R)c.bxl;
         byf_n = (R)c.byl;
         if (GR) {
           if (owner && q >= z0 && q < z1) {
-            p.Tout[(size_t)kk * plane + colq] = o.T;
+            if (p.Tout) p.Tout[(size_t)kk * plane + colq] = o.T;
             nit += o.iters;
             nmax = o.iters > nmax ? o.iters : nmax;
             nfb += o.fallback;
@@ -339,11 +366,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         bad |= o.bad;
       }
       if (ring) {
-        CellLoad rc;
-        load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        if (!ML) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
         PrimOut ro;
         R Wr[NF];
-        prim_cell<R, GR>(ph, p, rc, kk, mir, Wr, ro);
+        prim_cell<R, GR>(ph, p, rc, kk, mir, Wr, ro, maxit);
         bad |= ro.bad;
 #pragma unroll
         for (int f = 0; f < NF; ++f) sWn[f * LP + lw_ring] = Wr[f];
@@ -587,29 +613,33 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   }
 }
 
+size_t mlp_bytes() { return sizeof(MlpLds); }
+
+template <typename R>
+static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b, double cc,
+                           double dt_host, dim3 grid) {
+  const Phys &ph = c.ph;
+  dim3 block(NTHREADS);
+  if (!ph.gasrad)
+    hipLaunchKernelGGL((stage_kernel<R, false, false>), grid, block, 0, c.stream, ph, p, a, b,
+                       cc, dt_host, c.zseg);
+  else if (c.d.eos_guess == MHD_GUESS_MLP)
+    hipLaunchKernelGGL((stage_kernel<R, true, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
+                       dt_host, c.zseg);
+  else
+    hipLaunchKernelGGL((stage_kernel<R, true, false>), grid, block, 0, c.stream, ph, p, a, b,
+                       cc, dt_host, c.zseg);
+}
+
 hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
                         double cc, double dt_host) {
   const Phys &ph = c.ph;
   const int nblk = ((ph.nx + TB - 1) / TB) * ((ph.ny + TB - 1) / TB) * ((ph.nz + c.zseg - 1) / c.zseg);
   dim3 grid(nblk);
-  dim3 block(NTHREADS);
-  const bool gr = ph.gasrad != 0;
-  const bool split = c.d.precision == MHD_PREC_SPLIT;
-  if (split) {
-    if (gr)
-      hipLaunchKernelGGL((stage_kernel<float, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
-                         dt_host, c.zseg);
-    else
-      hipLaunchKernelGGL((stage_kernel<float, false>), grid, block, 0, c.stream, ph, p, a, b,
-                         cc, dt_host, c.zseg);
-  } else {
-    if (gr)
-      hipLaunchKernelGGL((stage_kernel<double, true>), grid, block, 0, c.stream, ph, p, a, b,
-                         cc, dt_host, c.zseg);
-    else
-      hipLaunchKernelGGL((stage_kernel<double, false>), grid, block, 0, c.stream, ph, p, a, b,
-                         cc, dt_host, c.zseg);
-  }
+  if (c.d.precision == MHD_PREC_SPLIT)
+    launch_stage_t<float>(c, p, a, b, cc, dt_host, grid);
+  else
+    launch_stage_t<double>(c, p, a, b, cc, dt_host, grid);
   return hipGetLastError();
 }
 
@@ -620,17 +650,28 @@ hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
 constexpr int RED_THREADS = 256;
 constexpr int RED_BLOCKS = 2048;
 
-template <bool GR>
+template <bool GR, bool ML>
 __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
     Phys ph, const double *__restrict__ U, const double *__restrict__ Bx,
     const double *__restrict__ By, const double *__restrict__ Bz,
-    const double *__restrict__ T, double *__restrict__ partial, int *flags) {
+    const double *__restrict__ T, const void *mlp, double *__restrict__ partial,
+    int *flags) {
+  __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
+  const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
+  if (ML) {
+    stage_mlp(mlp, sMlpRaw, threadIdx.x, RED_THREADS);
+    __syncthreads();
+  }
   const size_t plane = (size_t)ph.nx * ph.ny;
   const size_t n = plane * ph.nz;
+  const int lane = threadIdx.x & 63;
   double smax = 0.0;
   int bad = 0;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
+  // uniform trip count: lanes past the end redo the last cell and drop it
+  for (size_t base = (size_t)blockIdx.x * blockDim.x; base < n;
+       base += (size_t)gridDim.x * blockDim.x) {
+    const bool valid = base + threadIdx.x < n;
+    const size_t q = valid ? base + threadIdx.x : n - 1;
     const int i = (int)(q % ph.nx);
     const int j = (int)((q / ph.nx) % ph.ny);
     const int k = (int)(q / plane);
@@ -644,8 +685,15 @@ __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
     b[1] = 0.5 * (By[q] + By[q + (size_t)(jp - j) * ph.nx]);
     b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
     const double zero[4] = {0, 0, 0, 0};
+    double tg = (GR && !ML && T) ? T[q] : 0.0;
+    if (ML) {
+      float x0, x1;
+      mlp_inputs(ph, u[0], specific_eint(u, b), x0, x1);
+      tg = mlp_guess_wave(ph, sMlp, x0, x1, lane);
+    }
     PrimOut o;
-    cons2prim<GR>(ph, u, b, T ? T[q] : 0.0, zero, o);
+    cons2prim<GR>(ph, u, b, tg, zero, o, ML ? ph.newton_maxit_mlp : ph.newton_maxit);
+    if (!valid) continue;
     bad |= o.bad;
     const double rho = u[0];
     const double P = o.w[Q_P];
@@ -704,12 +752,15 @@ hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
   const size_t n = c.ncell;
   int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
   nb = nb < RED_BLOCKS ? nb : RED_BLOCKS;
-  if (c.ph.gasrad)
-    hipLaunchKernelGGL(signal_speed_kernel<true>, dim3(nb), dim3(RED_THREADS), 0, c.stream, c.ph,
-                       U, Bx, By, Bz, T, c.red, c.flags);
+  if (!c.ph.gasrad)
+    hipLaunchKernelGGL((signal_speed_kernel<false, false>), dim3(nb), dim3(RED_THREADS), 0,
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
+  else if (c.d.eos_guess == MHD_GUESS_MLP)
+    hipLaunchKernelGGL((signal_speed_kernel<true, true>), dim3(nb), dim3(RED_THREADS), 0,
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
   else
-    hipLaunchKernelGGL(signal_speed_kernel<false>, dim3(nb), dim3(RED_THREADS), 0, c.stream,
-                       c.ph, U, Bx, By, Bz, T, c.red, c.flags);
+    hipLaunchKernelGGL((signal_speed_kernel<true, false>), dim3(nb), dim3(RED_THREADS), 0,
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
   hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(RED_THREADS), 0, c.stream, c.red, nb, cfl,
                      dt_dev, c.red + RED_BLOCKS);
   return hipGetLastError();
@@ -719,10 +770,12 @@ hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
 // initial temperature (bracketed solve) for the previous-T guess
 // ---------------------------------------------------------------------------
 
+// T of every cell: Newton from Tg when given, else the bracketed solve
 __global__ void init_temperature_kernel(Phys ph, const double *__restrict__ U,
                                         const double *__restrict__ Bx,
                                         const double *__restrict__ By,
                                         const double *__restrict__ Bz,
+                                        const double *__restrict__ Tg,
                                         double *__restrict__ T, int *flags) {
   const size_t plane = (size_t)ph.nx * ph.ny;
   const size_t n = plane * ph.nz;
@@ -741,7 +794,7 @@ __global__ void init_temperature_kernel(Phys ph, const double *__restrict__ U,
     b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
     const double zero[4] = {0, 0, 0, 0};
     PrimOut o;
-    cons2prim<true>(ph, u, b, NAN, zero, o);
+    cons2prim<true>(ph, u, b, Tg ? Tg[q] : NAN, zero, o);
     if (o.bad) atomicOr(flags, o.bad);
     T[q] = o.T;
   }
@@ -749,11 +802,82 @@ __global__ void init_temperature_kernel(Phys ph, const double *__restrict__ U,
 
 hipError_t launch_init_temperature(const Ctx &c, const double *U,
                                    const double *Bx, const double *By,
-                                   const double *Bz, double *T) {
+                                   const double *Bz, const double *Tg, double *T) {
   int nb = (int)((c.ncell + 255) / 256);
   nb = nb < 4096 ? nb : 4096;
   hipLaunchKernelGGL(init_temperature_kernel, dim3(nb), dim3(256), 0, c.stream, c.ph, U, Bx, By,
-                     Bz, T, c.flags);
+                     Bz, Tg, T, c.flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batch temperature inversion T(rho, e_int) (EOS microbenchmark and guess
+// quality): guess from an array, the learned network or the bracket
+// ---------------------------------------------------------------------------
+
+template <bool ML>
+__global__ __launch_bounds__(256) void eos_solve_kernel(
+    Phys ph, const double *__restrict__ rho, const double *__restrict__ e,
+    const double *__restrict__ tguess, long long n, const void *mlp,
+    double *__restrict__ T, double *__restrict__ T0, unsigned long long *stats, int *flags) {
+  __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
+  const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
+  if (ML) {
+    stage_mlp(mlp, sMlpRaw, threadIdx.x, 256);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63;
+  unsigned long long it = 0, mx = 0, fb = 0;
+  int bad = 0;
+  for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
+       base += (long long)gridDim.x * blockDim.x) {
+    const bool valid = base + threadIdx.x < n;
+    const long long q = valid ? base + threadIdx.x : n - 1;
+    const double r = rho[q], ee = e[q];
+    double g = tguess ? tguess[q] : NAN;
+    if (ML) {
+      float x0, x1;
+      mlp_inputs(ph, r, ee, x0, x1);
+      g = mlp_guess_wave(ph, sMlp, x0, x1, lane);
+    }
+    double t = NAN;
+    int iters = 0, fallback = 0;
+    int rc = 1;
+    if (r > 0.0 && ee > 0.0)
+      rc = eos_temperature(ph, r, ee, g, ML ? ph.newton_maxit_mlp : ph.newton_maxit, t, iters,
+                           fallback);
+    if (!valid) continue;
+    T[q] = t;
+    if (T0) T0[q] = g;
+    it += iters;
+    mx = iters > mx ? iters : mx;
+    fb += fallback;
+    bad |= rc ? 2 : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    it += __shfl_xor(it, o);
+    fb += __shfl_xor(fb, o);
+    const unsigned long long m2 = __shfl_xor(mx, o);
+    mx = m2 > mx ? m2 : mx;
+  }
+  if (lane == 0) {
+    atomicAdd(&stats[0], it);
+    atomicMax(&stats[1], mx);
+    atomicAdd(&stats[2], fb);
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
+                            const double *tguess, long long n, double *T, double *T0) {
+  long long nb = (n + 255) / 256;
+  nb = nb < 8192 ? nb : 8192;
+  if (c.d.eos_guess == MHD_GUESS_MLP)
+    hipLaunchKernelGGL(eos_solve_kernel<true>, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph,
+                       rho, e, tguess, n, c.mlp, T, T0, c.nstats, c.flags);
+  else
+    hipLaunchKernelGGL(eos_solve_kernel<false>, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph,
+                       rho, e, tguess, n, c.mlp, T, T0, c.nstats, c.flags);
   return hipGetLastError();
 }
 

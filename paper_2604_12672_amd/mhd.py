@@ -52,9 +52,10 @@ class Diag(C.Structure):
     ]
 
 
-EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_state",
-           "mhd_compute_dt", "mhd_step", "mhd_advance", "mhd_get_state", "mhd_sync",
-           "mhd_diagnostics", "mhd_last_error", "mhd_destroy", "mhd_launch_info"]
+EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eos_mlp",
+           "mhd_eos_solve", "mhd_set_state", "mhd_compute_dt", "mhd_step", "mhd_advance",
+           "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
+           "mhd_launch_info"]
 
 _lib = None
 
@@ -72,6 +73,8 @@ def load():
     L.mhd_init_grid.argtypes = [C.POINTER(GridDesc), vp, C.POINTER(vp)]
     L.mhd_set_background.argtypes = [vp, vp, vp]
     L.mhd_set_sources.argtypes = [vp, vp, vp, C.c_int32]
+    L.mhd_set_eos_mlp.argtypes = [vp, vp, vp, vp, vp, vp, C.c_float, vp]
+    L.mhd_eos_solve.argtypes = [vp, vp, vp, vp, C.c_int64, vp, vp, C.POINTER(C.c_int64)]
     L.mhd_set_state.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
     L.mhd_compute_dt.argtypes = [vp, C.c_double, C.POINTER(C.c_double)]
     L.mhd_step.argtypes = [vp, C.c_double]
@@ -207,6 +210,27 @@ class Grid:
             assert tuple(force.shape) == (3,) + self.shape
         self._check(self._L.mhd_set_sources(self._h, _ptr(heat, HOST), _ptr(force, w), w))
 
+    def set_eos_mlp(self, model):
+        """Upload a paper_2604_12672_amd.eos_mlp.MLPGuess."""
+        w1, b1, w2, b2, w3, b3, norm = model.ctypes_args()
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._keep_mlp = (w1, b1, w2, b2, w3, norm)
+        self._check(self._L.mhd_set_eos_mlp(self._h, p(w1), p(b1), p(w2), p(b2), p(w3),
+                                            C.c_float(b3), p(norm)))
+
+    def eos_solve(self, rho, e, T_guess=None, with_guess=False):
+        """Invert T(rho, e) on the device for torch CUDA float64 tensors.
+        Returns (T, T0 or None, (newton steps, max steps, bracketed solves))."""
+        import torch
+        n = rho.numel()
+        T = torch.empty_like(rho)
+        T0 = torch.empty_like(rho) if with_guess else None
+        st = (C.c_int64 * 3)()
+        self._check(self._L.mhd_eos_solve(self._h, _ptr(rho, DEVICE), _ptr(e, DEVICE),
+                                          _ptr(T_guess, DEVICE), n, _ptr(T, DEVICE),
+                                          _ptr(T0, DEVICE), st))
+        return T, T0, tuple(st)
+
     def set_state(self, U, Bx, By, Bz, T=None):
         w = _where(U, Bx, By, Bz, T)
         self._check_shapes(U, Bx, By, Bz, T)
@@ -221,8 +245,11 @@ class Grid:
         if T is not None:
             assert tuple(T.shape) == sh
 
-    def load(self, w, guess=True):
-        """Set state, background and sources from a workloads.Workload."""
+    def load(self, w, guess=True, mlp=None):
+        """Set state, background and sources from a workloads.Workload (and
+        the guess network for MHD_GUESS_MLP contexts)."""
+        if mlp is not None:
+            self.set_eos_mlp(mlp)
         if w.bg_cc is not None:
             self.set_background(w.bg_cc, w.bg_fz)
         if w.heat is not None or w.force is not None:

@@ -1,0 +1,127 @@
+"""The learned guess on the GPU (MFMA inference): device guesses agree with
+the numpy emulation of the same BF16 network, the Newton polish reproduces
+the oracle's T, and the stage with the learned guess matches the oracle."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2604_12672_amd import eos_mlp
+from paper_2604_12672_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mhd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_12672_amd import mhd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2604_12672_amd import build
+        build.build()
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def model():
+    return eos_mlp.MLPGuess.load()
+
+
+def test_device_guess_matches_emulation(mhd, model):
+    import torch
+    p = wl.gasrad_params(4, 4, 4)
+    n = 100_003  # ragged: not a multiple of the block or the 64-lane pass
+    rho, e, T = eos_mlp.sample(p, n, seed=21)
+    g = mhd.Grid(p, eos_guess=mhd.GUESS_MLP)
+    g.set_eos_mlp(model)
+    Td, T0d, stats = g.eos_solve(torch.from_numpy(rho).cuda(), torch.from_numpy(e).cuda(),
+                                 with_guess=True)
+    g.close()
+    T0 = T0d.cpu().numpy()
+    em = model.predict_log10T(rho, e)
+    d = np.abs(np.log10(T0) - em)
+    print(f"guess vs emulation: median {np.median(d):.2e} max {d.max():.2e} dex", flush=True)
+    assert np.median(d) < 1e-4 and d.max() < 1e-2
+    ge = np.abs(np.log10(T0) - np.log10(T))
+    print(f"guess error: mean {ge.mean():.2e} max {ge.max():.2e} dex; newton steps "
+          f"{stats[0] / n:.2f}/sample, max {stats[1]}, fallbacks {stats[2]}", flush=True)
+    assert ge.mean() < 0.01
+    np.testing.assert_allclose(Td.cpu().numpy(), T, rtol=1.01e-11)
+    assert stats[2] == 0 and stats[1] <= 8
+
+
+def test_prev_t_batch_solve_and_bracket(mhd):
+    import torch
+    p = wl.gasrad_params(4, 4, 4)
+    n = 5000
+    rho, e, T = eos_mlp.sample(p, n, seed=22)
+    g = mhd.Grid(p)
+    r, ee = torch.from_numpy(rho).cuda(), torch.from_numpy(e).cuda()
+    Td, _, st = g.eos_solve(r, ee, torch.from_numpy(T * 1.2).cuda())
+    np.testing.assert_allclose(Td.cpu().numpy(), T, rtol=1.01e-11)
+    assert st[2] == 0
+    Td, _, st = g.eos_solve(r, ee)  # no guess: bracketed solve for every sample
+    assert st[2] == n
+    np.testing.assert_allclose(Td.cpu().numpy(), T, rtol=1.01e-11)
+    g.close()
+
+
+def rel_l2(a, b):
+    den = math.sqrt(float(np.sum(b * b)))
+    return math.sqrt(float(np.sum((a - b) ** 2))) / den if den > 0 else math.sqrt(float(np.sum(a * a)))
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_stage_with_learned_guess(mhd, model, precision, tol):
+    w = wl.smooth_box(18, 15, 12, eos=wl.EOS_GASRAD, bcz=1)
+    o = orc.Oracle(w.params, **w.extras())
+    ref = w.state()
+    dts = []
+    for _ in range(3):
+        dt = o.compute_dt(ref, w.cfl)
+        o.step(ref, dt)
+        dts.append(dt)
+    g = mhd.Grid(w.params, precision=precision, eos_guess=mhd.GUESS_MLP)
+    g.load(w, mlp=model)
+    for dt in dts:
+        g.step(dt)
+    out = g.get_state(with_T=True)
+    diag = g.diagnostics()
+    g.close()
+    for k in ("Bx", "By", "Bz"):
+        assert rel_l2(out[k], ref[k]) <= tol, k
+    for f in range(5):
+        assert rel_l2(out["U"][f], ref["U"][f]) <= tol, f
+    # temperature of the final state (the oracle's T array holds the last
+    # stage's solution, i.e. of U^(1))
+    _, Tfin = o.primitives(ref)
+    np.testing.assert_allclose(out["T"], Tfin, rtol=1e-9 if precision == 0 else 1e-5)
+    assert diag["divb_max"] < 1e-12
+    assert diag["fallbacks"] == 0
+    print(f"learned guess: {diag['newton_iters']} Newton steps in the last stage, "
+          f"max {diag['newton_max']}", flush=True)
+
+
+def test_learned_dt_matches_oracle(mhd, model):
+    w = wl.gasrad_box(16)
+    o = orc.Oracle(w.params, **w.extras())
+    dref = o.compute_dt(w.state(), 0.4)
+    g = mhd.Grid(w.params, eos_guess=mhd.GUESS_MLP)
+    g.load(w, mlp=model)
+    assert g.compute_dt(0.4) == pytest.approx(dref, rel=1e-10)
+    g.close()
+
+
+def test_learned_guess_requires_weights(mhd):
+    w = wl.gasrad_box(8)
+    g = mhd.Grid(w.params, eos_guess=mhd.GUESS_MLP)
+    g.set_state(w.U, w.Bx, w.By, w.Bz)
+    with pytest.raises(mhd.MHDError) as e:
+        g.step(1e-4)
+    assert e.value.code == -6
+    g.close()
