@@ -1,18 +1,24 @@
 """Benchmark of the explicit MHD step on one MI355X.
 
-Workload: the 3D stratified MHD box at 256^3 (n = 1.5 polytrope, gamma =
-5/3, four pressure scale heights, isobaric 1e-4 density noise, seed field at
-beta = 1e6, periodic x/y, reflecting z), SSP-RK2, CFL 0.4.  A step is the
-whole hot path: the CFL reduction and the two fused stage kernels
+Headline workload: the 3D stratified MHD box at 256^3 (n = 1.5 polytrope,
+gamma = 5/3, four pressure scale heights, isobaric 1e-4 density noise, seed
+field at beta = 1e6, periodic x/y, reflecting z), SSP-RK2, CFL 0.4.  A step
+is the whole hot path: the CFL reduction and the two fused stage kernels
 (primitive recovery, van Leer reconstruction, LHLLD fluxes, Contact-CT EMFs,
 cell and face updates), with the state resident in HBM.
 
-Printed: one JSON line with zone-updates/s of the FP64 path (`value`), the
-roofline of its dominant kernel (the stage kernel), the same for the split
-precision path, and the FP64 oracle timed on the host cores on a bounded
-sample of the same workload.
+Printed: one JSON line with zone-updates/s of the FP64 path (`value`) and the
+roofline of its dominant kernel (the stage kernel); the split-precision path
+on the same box; the gas+radiation box at 256^3 (FP64 with the previous-T
+guess against split precision with the learned guess); the batch EOS
+inversion (learned guess against the bracketed solve); the split path's
+per-field error after 50 steps of the 512^3 box with heating and cooling;
+the 384^3 forced turbulence box (learned guess, split precision); and the
+FP64 oracle timed on the host cores on a bounded sample of the headline
+workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -23,38 +29,75 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per zone-update of one SSP-RK2 step: stage 1 reads U^n
-# (5 + 3 FP64 = 64 B) and writes U^(1) (64 B); stage 2 reads U^n and U^(1)
-# and writes U^(n+1) -> 128 + 192 = 320 B; per stage launch on average 160 B.
-BYTES_PER_ZONE_STEP = 320.0
-BYTES_PER_ZONE_STAGE = BYTES_PER_ZONE_STEP / 2.0
+# Algorithmic bytes per zone of one stage launch (FP64 state, each array
+# touched once): stage 1 reads U^n (5 cell + 3 face values = 64 B) and writes
+# U^(1) (64 B); stage 2 reads U^n and U^(1) and writes U^(n+1): 128 + 192 =
+# 320 B per SSP-RK2 step, 160 B per stage launch on average.  The gas +
+# radiation EOS adds the temperature guess read and the solution written
+# (16 B) when Newton starts from the previous temperature (the learned guess
+# needs no stored temperature); a forcing field adds its three components
+# (24 B).
+BYTES_STATE_STAGE = 160.0
+BYTES_T_STAGE = 16.0
+BYTES_FORCE_STAGE = 24.0
 METRIC = "zone-updates/s (3D MHD 256^3) FP64 vs FP32+learned-EOS; % HBM roofline"
+
+# HBM traffic of the stage kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (average KiB per dispatch over the timed launches), keyed
+# by the digest of the kernel sources the counters were taken on.  The
+# factors scale the counters to bytes: a plain 1 GiB read + 1 GiB write
+# kernel reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB on this chip.
+FETCH_FACTOR = 2.0
+WRITE_FACTOR = 1.0
+TRAFFIC_KIB = {
+    # digest: {path: (fetch KiB, write KiB) per stage dispatch}
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def gpu_run(mhd, w, precision, steps, warmup, cfl):
+def kernel_digest():
+    """sha256 over the HIP sources of the library (first 16 hex digits)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2604_12672_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(path):
+    t = TRAFFIC_KIB.get(kernel_digest(), {}).get(path)
+    if t is None:
+        return None
+    return (t[0] * FETCH_FACTOR + t[1] * WRITE_FACTOR) * 1024.0
+
+
+def gpu_run(mhd, w, precision, steps, warmup, mlp=None):
+    """Whole-step throughput with mhd_advance (device dt, no host round
+    trip), then the stage kernel's duration from HIP events on the library's
+    stream around fixed-dt steps (only the two stage launches run between
+    the events)."""
     import torch
-    g = mhd.Grid(w.params, precision=precision)
-    g.load(w)
+    guess = mhd.GUESS_MLP if mlp is not None else mhd.GUESS_PREV_T
+    g = mhd.Grid(w.params, precision=precision, eos_guess=guess)
+    g.load(w, mlp=mlp)
     stream = torch.cuda.current_stream()
-    g.advance(cfl, warmup)
+    g.advance(w.cfl, warmup)
     g.sync()
     torch.cuda.synchronize()
-    # whole-step throughput: device-side dt + both stages, no host round trip
     t0 = time.perf_counter()
-    g.advance(cfl, steps)
+    g.advance(w.cfl, steps)
     g.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # stage-kernel duration with HIP events on the library's stream: a fixed
-    # dt so that only the two stage launches run between the events
-    dt = g.compute_dt(cfl)
+    diag = g.diagnostics()
+    dt = g.compute_dt(w.cfl)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    nrep = max(steps, 4)
+    nrep = max(min(steps, 50), 4)
     e0.record(stream)
     for _ in range(nrep):
         g.step(dt)
@@ -62,17 +105,124 @@ def gpu_run(mhd, w, precision, steps, warmup, cfl):
     e1.synchronize()
     g.sync()
     stage_ms = e0.elapsed_time(e1) / (2.0 * nrep)
-    diag = g.diagnostics()
     info = g.launch_info()
     g.close()
-    return wall, stage_ms, diag, info
+    return {"wall": wall, "stage_ms": stage_ms, "diag": diag, "info": info,
+            "ms": wall / steps * 1e3, "value": w.ncells * steps / wall, "learned": mlp is not None}
 
 
-def roofline(ncell, stage_ms):
-    achieved = BYTES_PER_ZONE_STAGE * ncell / (stage_ms * 1e-3) / 1e9
+def stage_bytes(w, learned):
+    b = BYTES_STATE_STAGE
+    if w.T is not None and not learned:
+        b += BYTES_T_STAGE
+    if w.force is not None:
+        b += BYTES_FORCE_STAGE
+    return b
+
+
+def roofline(w, stage_ms, path, learned=False):
+    per_zone = stage_bytes(w, learned)
+    per_launch = per_zone * w.ncells
+    achieved = per_launch / (stage_ms * 1e-3) / 1e9
+    tr = traffic_bytes(path)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "stage_kernel", "bytes_per_zone_stage": BYTES_PER_ZONE_STAGE}
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else round(tr),
+            "kernel": "stage_kernel", "stage_ms": round(stage_ms, 4),
+            "bytes_per_zone_stage": per_zone, "algorithmic_bytes_per_launch": round(per_launch)}
+
+
+def newton_stats(w, diag):
+    return {"newton_steps_per_cell": round(diag["newton_iters"] / w.ncells, 3),
+            "newton_max": diag["newton_max"], "fallbacks": diag["fallbacks"]}
+
+
+def eos_bench(mhd, model, n):
+    """Batch inversion of n iid (rho, T) samples log-uniform over the
+    gas+radiation range: learned guess + Newton polish against the bracketed
+    solve, both on the device (HIP events around each call)."""
+    import numpy as np
+    import torch
+    from paper_2604_12672_amd import workloads as wl
+    p = wl.gasrad_params(4, 4, 4)
+    rho, T = wl.eos_samples(n)
+    _, e = wl.gasrad_forward(p, rho, T)
+    r = torch.from_numpy(rho).cuda()
+    ee = torch.from_numpy(e).cuda()
+    out = {}
+    for name, guess in (("learned", mhd.GUESS_MLP), ("bracketed", mhd.GUESS_PREV_T)):
+        g = mhd.Grid(p, eos_guess=guess)
+        if guess == mhd.GUESS_MLP:
+            g.set_eos_mlp(model)
+        g.eos_solve(r, ee)  # warm-up
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        Td, T0, st = g.eos_solve(r, ee, with_guess=(guess == mhd.GUESS_MLP))
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        g.close()
+        Th = Td.cpu().numpy()
+        res = {"ms": round(ms, 4), "solves_per_s": round(n / (ms * 1e-3), 1),
+               "newton_steps_per_cell": round(st[0] / n, 3), "newton_max": int(st[1]),
+               "bracketed_solves": int(st[2]),
+               "max_rel_err_vs_exact_T": float(np.max(np.abs(Th - T) / T))}
+        if T0 is not None:
+            d = np.abs(np.log10(T0.cpu().numpy()) - np.log10(T))
+            res["guess_mean_abs_dlog10T"] = float(d.mean())
+            res["guess_max_abs_dlog10T"] = float(d.max())
+        out[name] = res
+        log(f"bench: eos {name}: {res}")
+    out["speedup_learned_vs_bracketed"] = round(out["bracketed"]["ms"] / out["learned"]["ms"], 3)
+    out["samples"] = f"{n} iid (rho, T) log-uniform over [1e-2, 1e2] x [1e5, 1e8] K"
+    return out
+
+
+def split_error(mhd, n, steps):
+    """Per-field rel L2 of the split path against the FP64 path after
+    `steps` steps of the stratified box with heating and cooling at n^3, the
+    same dt sequence on both (taken from the FP64 run).  The FP64 GPU path
+    stands in for the oracle at this size (it matches the oracle to 1e-12 in
+    the windowed full-size parity tests)."""
+    import torch
+    from paper_2604_12672_amd import workloads as wl
+    w = wl.stratified_box(n, heating=True, steps=steps)
+    g64 = mhd.Grid(w.params, precision=mhd.PREC_FP64)
+    g64.load(w)
+    g32 = mhd.Grid(w.params, precision=mhd.PREC_SPLIT)
+    g32.load(w)
+    del w
+    for _ in range(steps):
+        dt = g64.compute_dt(0.4)
+        g64.step(dt)
+        g32.step(dt)
+    sh = g64.shape
+    outs = []
+    for g in (g64, g32):
+        o = {"U": torch.empty((5,) + sh, dtype=torch.float64, device="cuda"),
+             "Bx": torch.empty(sh, dtype=torch.float64, device="cuda"),
+             "By": torch.empty(sh, dtype=torch.float64, device="cuda"),
+             "Bz": torch.empty((g.nzf,) + sh[1:], dtype=torch.float64, device="cuda")}
+        g.get_state(out=o)
+        outs.append(o)
+    d32 = g32.diagnostics()
+    g64.close()
+    g32.close()
+    errs = {}
+    names = [("U", 0, "rho"), ("U", 1, "m_x"), ("U", 2, "m_y"), ("U", 3, "m_z"), ("U", 4, "E"),
+             ("Bx", None, "B_x"), ("By", None, "B_y"), ("Bz", None, "B_z")]
+    for key, c, name in names:
+        a = outs[1][key] if c is None else outs[1][key][c]
+        b = outs[0][key] if c is None else outs[0][key][c]
+        den = float(torch.linalg.vector_norm(b))
+        errs[name] = float(torch.linalg.vector_norm(a - b)) / den if den > 0 else None
+    return {"grid": [n, n, n], "steps": steps, "rel_l2_vs_fp64": errs,
+            "max_rel_l2": max(v for v in errs.values() if v is not None),
+            "divb_max": d32["divb_max"],
+            "reference": "FP64 GPU path (oracle-matched), same dt sequence"}
 
 
 def cpu_baseline(n, target_s=12.0):
@@ -97,25 +247,37 @@ def cpu_baseline(n, target_s=12.0):
             "sample": f"stratified box {n}^3, {steps} SSP-RK2 steps incl. CFL, {el:.1f} s"}
 
 
+def summary(w, r, path):
+    return {"value": round(r["value"], 1), "ms_per_step": round(r["ms"], 4),
+            "roofline": roofline(w, r["stage_ms"], path, r["learned"]), "divb_max": r["diag"]["divb_max"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=256, help="linear grid size")
-    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--n", type=int, default=256, help="linear grid size of the headline box")
+    ap.add_argument("--only", choices=["fp64", "split"], default=None,
+                    help="run only this path of the headline box (profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline box only (no gas+radiation, EOS, 512^3, turbulence)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96)
-    ap.add_argument("--only", choices=["fp64", "split"], default=None)
+    ap.add_argument("--eos-n", type=int, default=256 ** 3)
+    ap.add_argument("--split-n", type=int, default=512)
+    ap.add_argument("--split-steps", type=int, default=50)
+    ap.add_argument("--turb-n", type=int, default=384)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the halo-exchange design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
+    from paper_2604_12672_amd import eos_mlp
     from paper_2604_12672_amd import mhd
     from paper_2604_12672_amd import workloads as wl
     if not os.path.exists(mhd.LIB_PATH):
@@ -124,20 +286,17 @@ def main():
     mhd.load()
     torch.cuda.set_device(0)
     n = args.n
-    log(f"bench: building stratified box {n}^3")
+    log(f"bench: stratified box {n}^3 (kernel sources {kernel_digest()})")
     w = wl.stratified_box(n)
-    cfl = w.cfl
     res = {}
     for name, prec in (("fp64", mhd.PREC_FP64), ("split", mhd.PREC_SPLIT)):
         if args.only and args.only != name:
             continue
-        if name == "split" and args.no_split:
-            continue
         log(f"bench: {name} warmup={args.warmup} steps={args.steps}")
-        wall, stage_ms, diag, info = gpu_run(mhd, w, prec, args.steps, args.warmup, cfl)
-        res[name] = dict(wall=wall, stage_ms=stage_ms, diag=diag, info=info)
-        log(f"bench: {name} {wall / args.steps * 1e3:.3f} ms/step, stage {stage_ms:.3f} ms, "
-            f"divB {diag['divb_max']:.2e}")
+        r = gpu_run(mhd, w, prec, args.steps, args.warmup)
+        res[name] = r
+        log(f"bench: {name} {r['ms']:.3f} ms/step, stage {r['stage_ms']:.3f} ms, "
+            f"divB {r['diag']['divb_max']:.2e}")
     if args.calib_copy:
         # plain streaming kernel of known size: reads 2^30 bytes, writes 2^30
         a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
@@ -145,33 +304,63 @@ def main():
         torch.cuda.synchronize()
         torch.add(a, 1.0, out=b)
         torch.cuda.synchronize()
+        del a, b
         log("bench: calibration copy of 1 GiB done")
     main_name = "fp64" if "fp64" in res else "split"
     r = res[main_name]
-    ms = r["wall"] / args.steps * 1e3
-    value = w.ncells * args.steps / r["wall"]
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "zone-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "metric": METRIC, "value": round(r["value"], 1), "unit": "zone-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if main_name == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"stratified MHD box {n}^3 (n=1.5 polytrope, 4 H_P, beta 1e6 "
-                               f"seed field, periodic x/y, reflecting z), SSP-RK2, CFL {cfl}, "
-                               f"van Leer + LHLLD + Contact-CT, ideal gas, {main_name} path",
+        "config": {"workload": f"stratified MHD box {n}^3 (n=1.5 polytrope, 4 H_P, 1e-4 density "
+                               f"noise, beta 1e6 seed field, periodic x/y, reflecting z), SSP-RK2, "
+                               f"CFL {w.cfl}, van Leer + LHLLD + Contact-CT, ideal gas, "
+                               f"{main_name} path",
                    "cells": w.ncells, "grid": [n, n, n], "precision": main_name,
-                   "launch": r["info"]},
-        "roofline": roofline(w.ncells, r["stage_ms"]),
+                   "launch": r["info"], "kernel_sources": kernel_digest()},
+        "roofline": roofline(w, r["stage_ms"], main_name),
         "divb_max": r["diag"]["divb_max"],
     }
     if "split" in res and main_name == "fp64":
-        s = res["split"]
-        sms = s["wall"] / args.steps * 1e3
-        out["split"] = {"value": round(w.ncells * args.steps / s["wall"], 1),
-                        "ms_per_step": round(sms, 4), "dtype": "f32 flux/recon/EMF, f64 rest",
-                        "speedup_vs_fp64": round(ms / sms, 3),
-                        "roofline": roofline(w.ncells, s["stage_ms"]),
-                        "divb_max": s["diag"]["divb_max"]}
+        s = summary(w, res["split"], "split")
+        s["dtype"] = "f32 recon/flux/EMF on deviations, f64 background/accumulation"
+        s["speedup_vs_fp64"] = round(r["ms"] / res["split"]["ms"], 3)
+        out["split"] = s
+    del w
+    if not args.no_extras and not args.only:
+        model = eos_mlp.MLPGuess.load()
+        # gas + radiation box: plain FP64 step (previous-T guess) against the
+        # split step with the learned guess
+        log("bench: gas+radiation box 256^3")
+        wg = wl.config(3)
+        g64 = gpu_run(mhd, wg, mhd.PREC_FP64, args.steps, args.warmup)
+        gml = gpu_run(mhd, wg, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
+        gas = {"fp64_prev_t": dict(summary(wg, g64, "gasrad_fp64"), **newton_stats(wg, g64["diag"])),
+               "split_learned": dict(summary(wg, gml, "gasrad_split_learned"),
+                                     **newton_stats(wg, gml["diag"])),
+               "speedup_split_learned_vs_fp64": round(g64["ms"] / gml["ms"], 3),
+               "workload": "gas+radiation box 256^3, log-uniform rho in [1e-2, 1e2] and "
+                           "T in [1e5, 1e8] K, beta 1e6, periodic"}
+        out["gasrad"] = gas
+        log(f"bench: gasrad fp64 {g64['ms']:.3f} ms/step, split+learned {gml['ms']:.3f} ms/step")
+        del wg
+        log("bench: batch EOS inversion")
+        out["eos_solve"] = eos_bench(mhd, model, args.eos_n)
+        log(f"bench: split error, stratified box {args.split_n}^3 with heating, "
+            f"{args.split_steps} steps")
+        out["split_error"] = split_error(mhd, args.split_n, args.split_steps)
+        log(f"bench: split error {out['split_error']['rel_l2_vs_fp64']}")
+        log(f"bench: turbulence box {args.turb_n}^3")
+        wt = wl.turbulence_box(args.turb_n)
+        tr = gpu_run(mhd, wt, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
+        t = dict(summary(wt, tr, "turbulence_split_learned"), **newton_stats(wt, tr["diag"]))
+        t["workload"] = (f"forced MHD turbulence {args.turb_n}^3, rms Mach 3, beta 1, "
+                         f"gas+radiation, learned guess, split precision")
+        out["turbulence"] = t
+        log(f"bench: turbulence {tr['ms']:.3f} ms/step, divB {tr['diag']['divb_max']:.2e}")
+        del wt
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle) {args.cpu_n}^3")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)

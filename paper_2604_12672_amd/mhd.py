@@ -68,6 +68,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2604_12672_amd.build`")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+    # the library binds to, so streams and device pointers are shared.  The
+    # other order would load a second HIP runtime into the process.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     L.mhd_init_grid.argtypes = [C.POINTER(GridDesc), vp, C.POINTER(vp)]

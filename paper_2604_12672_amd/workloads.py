@@ -438,16 +438,26 @@ def turbulence_box(n=384, seed=3, mach=3.0, beta=1.0, rho0=1e-2, T0=1e7, cfl=0.4
     ks = [(a, b, c) for a in range(-2, 3) for b in range(-2, 3) for c in range(-2, 3)
           if 1 <= a * a + b * b + c * c <= 4]
     shp = (n, n, n)
-    v = np.zeros((3,) + shp)
-    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    # v_c = sum_k a_c cos(2 pi k.x + phi) = Re sum_kz e^{2 pi i kz z} G_c,kz(y, x)
+    # with G_c,kz = sum_{kx,ky} a_c e^{i phi} e^{2 pi i (kx x + ky y)}: one
+    # real matrix product per component instead of a cosine per mode and cell
+    G = np.zeros((3, 5, n, n), dtype=complex)
+    ex = {m: np.exp(2j * np.pi * m * xc) for m in range(-2, 3)}
+    ey = {m: np.exp(2j * np.pi * m * yc) for m in range(-2, 3)}
     for k in ks:
         kv = np.array(k, dtype=float)
         a = rng.normal(size=3)
         a = a - kv * (kv @ a) / (kv @ kv)
         phi = rng.uniform(0.0, 2.0 * math.pi)
-        ph = np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + phi)
+        plane = np.exp(1j * phi) * np.outer(ey[k[1]], ex[k[0]])
         for c in range(3):
-            v[c] += a[c] * ph
+            G[c, k[2] + 2] += a[c] * plane
+    ez = np.stack([np.exp(2j * np.pi * m * zc) for m in range(-2, 3)], axis=1)  # [n, 5]
+    lhs = np.concatenate([ez.real, -ez.imag], axis=1)                          # [n, 10]
+    v = np.empty((3,) + shp)
+    for c in range(3):
+        rhs = np.concatenate([G[c].real.reshape(5, -1), G[c].imag.reshape(5, -1)], axis=0)
+        v[c] = (lhs @ rhs).reshape(shp)
     rho = np.full(shp, rho0)
     T = np.full(shp, T0)
     P, e = gasrad_forward(p, rho, T)
