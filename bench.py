@@ -51,6 +51,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
+    "caaef8f9d822d98c": {"fp64": (1368092.9, 1059482.8), "split": (1707388.5, 1159491.2)},
 }
 
 
@@ -132,9 +133,10 @@ def roofline(w, stage_ms, path, learned=False):
             "bytes_per_zone_stage": per_zone, "algorithmic_bytes_per_launch": round(per_launch)}
 
 
-def newton_stats(w, diag):
-    return {"newton_steps_per_cell": round(diag["newton_iters"] / w.ncells, 3),
-            "newton_max": diag["newton_max"], "fallbacks": diag["fallbacks"]}
+def newton_stats(w, diag, stages=2):
+    """Newton statistics of the last step (all its stages)."""
+    return {"newton_steps_per_cell_stage": round(diag["newton_iters"] / (w.ncells * stages), 3),
+            "newton_max": diag["newton_max"], "fallback_cell_stages": diag["fallbacks"]}
 
 
 def eos_bench(mhd, model, n):

@@ -103,9 +103,11 @@ typedef struct {
   double bface_max;       /* max |B_face|                                      */
   double total[5];        /* sums over cells of rho, m_x, m_y, m_z, E          */
   double bflux_x0;        /* sum of Bx over the plane x_{-1/2}                 */
-  int64_t newton_iters;   /* Newton steps taken in the last stage              */
-  int64_t newton_max;     /* largest Newton count of one cell, last stage      */
-  int64_t fallbacks;      /* cells that needed the bracketed solve, last stage */
+  int64_t newton_iters;   /* Newton steps of the owned cells, summed over the
+                             stages of the last step                          */
+  int64_t newton_max;     /* largest Newton count of one cell-stage, last step */
+  int64_t fallbacks;      /* cell-stages that needed the bracketed solve,
+                             last step                                        */
   int32_t error_flags;    /* latched device flags (bit 0 unphysical, bit 1 EOS) */
 } mhd_diag;
 

@@ -171,7 +171,7 @@ def test_gasrad_256_full_oracle(mhd, mode):
     out, diag, _ = gpu_run(mhd, w, 1, 1 if mode.endswith("split") else 0, mlp=mlp, dts=[dt])
     fo, fr = fields(out), fields(ref)
     errs = {k: rel_l2(fo[k], fr[k]) for k in FIELDS}
-    print(mode, "rel L2:", errs, "newton steps (last stage):", diag["newton_iters"],
+    print(mode, "rel L2:", errs, "newton steps (last step):", diag["newton_iters"],
           "fallbacks:", diag["fallbacks"], flush=True)
     tol = 1e-5 if mode.endswith("split") else 1e-9
     assert all(v <= tol for v in errs.values()), errs

@@ -103,7 +103,7 @@ def test_stage_with_learned_guess(mhd, model, precision, tol):
     np.testing.assert_allclose(out["T"], Tfin, rtol=1e-9 if precision == 0 else 1e-5)
     assert diag["divb_max"] < 1e-12
     assert diag["fallbacks"] == 0
-    print(f"learned guess: {diag['newton_iters']} Newton steps in the last stage, "
+    print(f"learned guess: {diag['newton_iters']} Newton steps in the last step, "
           f"max {diag['newton_max']}", flush=True)
 
 
