@@ -6,12 +6,17 @@ waves, point symmetry of the Orszag-Tang data, Brio-Wu self-convergence
 limit of Contact-CT, closed-form source terms and the SSP-RK temporal
 orders (Sect. 2.9)."""
 import math
+import os
+import sys
 
 import numpy as np
 import pytest
 
 from oracle import orc
 from paper_2604_12672_amd import workloads as wl
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from read import read  # noqa: E402
 
 
 def run(w, nsteps=None, t_end=None, params=None, dts=None):
@@ -228,8 +233,9 @@ def test_orszag_tang_point_symmetry():
 
 
 def _bw_profile(n, axis=0):
+    """Brio-Wu tube at the paper's output time (tests/golden/brio_wu.txt)."""
     w = wl.brio_wu(n, axis=axis)
-    o, st, _ = run(w, t_end=0.08)
+    o, st, _ = run(w, t_end=read("brio_wu.txt")["t_end"])
     return w, st
 
 
