@@ -208,7 +208,7 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   c.zseg = 32;
   if (const char *zs = std::getenv("MHD_ZSEG")) {
     const int v = std::atoi(zs);
-    if (v >= 1 && v <= 4096) c.zseg = v;
+    if (v >= 1 && v <= mhd::ZSEG_MAX) c.zseg = v;
   }
   if (c.zseg > desc->nz) c.zseg = desc->nz;
 

@@ -16,6 +16,9 @@ namespace mhd {
 constexpr int TT = 16;        // threads per tile edge
 constexpr int TB = TT - 2;    // output columns per tile edge
 constexpr int NTHREADS = TT * TT;
+// Longest z segment of a stage block (the block stages the background
+// profile of its segment and halo in LDS).
+constexpr int ZSEG_MAX = 64;
 
 // Physics and grid constants passed by value to every kernel.
 struct Phys {

@@ -104,14 +104,9 @@ struct Cfg {
 
 // primitive deviations of one cell, as R, with the mirror image applied
 template <typename R, bool GR>
-__device__ __forceinline__ void prim_cell(const Phys &ph, const StagePtrs &p,
-                                          const CellLoad &c, int kk, int mirror,
-                                          R *w, PrimOut &o, int maxit = -1) {
-  double bg[4];
-  bg[0] = p.bg_cc[kk];
-  bg[1] = p.bg_cc[ph.nz + kk];
-  bg[2] = p.bg_cc[2 * ph.nz + kk];
-  bg[3] = p.bg_cc[3 * ph.nz + kk];
+__device__ __forceinline__ void prim_cell(const Phys &ph, const CellLoad &c,
+                                          const double bg[4], int mirror, R *w,
+                                          PrimOut &o, int maxit = -1) {
   cons2prim<GR>(ph, c.u, c.b, c.tg, bg, o, maxit);
   constexpr int NF = Cfg<R, GR>::NF;
 #pragma unroll
@@ -231,6 +226,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   static_assert(!ML || GR, "the learned guess belongs to the gas+radiation EOS");
   static_assert(sizeof(MlpLds) % 16 == 0, "MlpLds is copied in 16-byte words");
   constexpr int NF = Cfg<R, GR>::NF;
+  constexpr bool EARLY = sizeof(R) == 8 || !GR || ML;
+  // FP64 runs one wave per SIMD (register-bound): it has the registers to
+  // hold the next plane's cell data while it works on the current one
+  constexpr bool PREFETCH = sizeof(R) == 8;
   __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
   const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
   if (ML) {
@@ -273,6 +272,26 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   const int gi = wrapi(gx, ph.nx), gip = wrapi(gx + 1, ph.nx);
   const int gj = wrapi(gy, ph.ny), gjp = wrapi(gy + 1, ph.ny);
   const bool owner = ci >= 0 && ci < TB && cj >= 0 && cj < TB && gx < ph.nx && gy < ph.ny;
+
+  // Background profile (and heating) of the planes this block touches,
+  // staged once: cell planes q = z0-2 .. z1+1 (mirror / wrap applied) and
+  // z faces z0 .. z1.  Uniform per plane, so every read is a broadcast.
+  __shared__ double sBc[5][ZSEG_MAX + 4];  // rho, P, gamma_e, gamma_c, heat
+  __shared__ double sBf[4][ZSEG_MAX + 1];
+  {
+    const int nq = z1 - z0 + 4, nf = z1 - z0 + 1;
+    for (int i = threadIdx.x; i < 5 * nq; i += NTHREADS) {
+      const int f = i / nq, j = i - f * nq;
+      int mir;
+      const int kk = zsource(ph, z0 - 2 + j, mir);
+      sBc[f][j] = f < 4 ? p.bg_cc[f * ph.nz + kk] : (p.heat ? p.heat[kk] : 0.0);
+    }
+    for (int i = threadIdx.x; i < 4 * nf; i += NTHREADS) {
+      const int f = i / nf, j = i - f * nf;
+      sBf[f][j] = p.bg_fz[f * ph.nzf + zface(ph, z0 + j)];
+    }
+  }
+  __syncthreads();
   const size_t plane = (size_t)ph.nx * ph.ny;
   const size_t ncell = plane * ph.nz;
   const size_t colq = (size_t)gj * ph.nx + gi;
@@ -321,12 +340,52 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
 #pragma unroll
   for (int f = 0; f < NF; ++f) Wc[f] = R(0);
 
+  CellLoad pc{}, prc{};  // prefetched cell data of the next P1 plane
+  if (PREFETCH) {
+    int mir0;
+    const int k0 = zsource(ph, z0 - 2, mir0);
+    load_cell(ph, p, gi, gip, gj, gjp, k0, mir0, pc);
+    if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, k0, mir0, prc);
+  }
   for (int k = z0 - 4; k < z1; ++k) {
+    // every global value P3 and P4 read, requested together: at the top of
+    // the plane so that the latency overlaps P1 and P2, except where the
+    // registers that costs would lower the occupancy (FP32 gas+radiation
+    // with the stored guess), then at the start of P3
+    const bool upd = k >= z0 && owner;
+    const bool updz = k >= z0 - 1 && k + 1 < z1 && owner && !(ph.reflect && k + 1 == 0);
+    const bool base = ca != 0.0;
+    const size_t qc = (size_t)(k > 0 ? k : 0) * plane + colq;
+    const size_t qfz = (size_t)(k + 1 > 0 ? k + 1 : 0) * plane + colq;
+    double us[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0}, fo[3] = {0, 0, 0};
+    double bxs = 0.0, bys = 0.0, bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
+    auto load_update = [&]() {
+      if (upd) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + qc];
+        bxs = p.Bxs[qc];
+        bys = p.Bys[qc];
+        if (base) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) u0[f] = p.U0[f * ncell + qc];
+          bx0 = p.Bx0[qc];
+          by0 = p.By0[qc];
+        }
+        if (p.force) {
+          fo[0] = p.force[qc];
+          fo[1] = p.force[ncell + qc];
+          fo[2] = p.force[2 * ncell + qc];
+        }
+      }
+      if (updz && base) bz0 = p.Bz0[qfz];
+    };
+    if (EARLY) load_update();
     // ---------------- P1 ------------------------------------------------
     // primitives of plane k+2 (staged in LDS), z reconstruction of cell
     // k+1 and the z-face k+1/2, x/y reconstruction of cell k+1
     R Wn[NF];
     R bxf_n, byf_n;
+    double bzf = 0.0;  // B_z on the z-face k+1/2 (read again by P4)
     R fzc[5] = {0, 0, 0, 0, 0};
     R zf_ey = 0, zf_ex = 0, zf_m = 0;
     Side<R> xl{}, xll{}, yl{};
@@ -337,9 +396,21 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       const int kk = zsource(ph, q, mir);
       R *sWn = &sW[q & 1][0][0];
       CellLoad c, rc;
-      load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+      if (PREFETCH) {
+        // plane q arrived during the previous plane; request plane q+1
+        c = pc;
+        rc = prc;
+        if (k + 1 < z1) {
+          int mirn;
+          const int kn = zsource(ph, q + 1, mirn);
+          load_cell(ph, p, gi, gip, gj, gjp, kn, mirn, pc);
+          if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, kn, mirn, prc);
+        }
+      } else {
+        load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+      }
       if (ML) {
-        if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        if (ring && !PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
         // learned guesses for the own cells (two passes) and for the ring
         // cells of lanes 0..15 (one pass); every lane takes part
         float x0, x1, r0 = 0.0f, r1 = 0.0f;
@@ -350,9 +421,11 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         rc.tg = tr;
       }
       const int maxit = ML ? ph.newton_maxit_mlp : ph.newton_maxit;
+      const int jq = q - (z0 - 2);
+      const double bgq[4] = {sBc[0][jq], sBc[1][jq], sBc[2][jq], sBc[3][jq]};
       {
         PrimOut o;
-        prim_cell<R, GR>(ph, p, c, kk, mir, Wn, o, maxit);
+        prim_cell<R, GR>(ph, c, bgq, mir, Wn, o, maxit);
         bxf_n = (R)c.bxl;
         byf_n = (R)c.byl;
         if (GR) {
@@ -366,10 +439,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         bad |= o.bad;
       }
       if (ring) {
-        if (!ML) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        if (!ML && !PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
         PrimOut ro;
         R Wr[NF];
-        prim_cell<R, GR>(ph, p, rc, kk, mir, Wr, ro, maxit);
+        prim_cell<R, GR>(ph, rc, bgq, mir, Wr, ro, maxit);
         bad |= ro.bad;
 #pragma unroll
         for (int f = 0; f < NF; ++f) sWn[f * LP + lw_ring] = Wr[f];
@@ -388,12 +461,13 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         if (k >= z0 - 1) {
           const int fzi = zface(ph, k + 1);
           FaceBg<R> bgf;
-          const int nzf = ph.nzf;
-          bgf.rho = (R)p.bg_fz[fzi];
-          bgf.p = (R)p.bg_fz[nzf + fzi];
-          bgf.ge = (R)p.bg_fz[2 * nzf + fzi];
-          bgf.gc = (R)p.bg_fz[3 * nzf + fzi];
-          const R bzn = (R)p.Bzs[(size_t)fzi * plane + colq];
+          const int jf = k + 1 - z0;
+          bgf.rho = (R)sBf[0][jf];
+          bgf.p = (R)sBf[1][jf];
+          bgf.ge = (R)sBf[2][jf];
+          bgf.gc = (R)sBf[3][jf];
+          bzf = p.Bzs[(size_t)fzi * plane + colq];
+          const R bzn = (R)bzf;
           R fz[7];
           riemann<R, GR>(topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut, imcut, fz);
           to_cons<R>(2, fz, fzc);
@@ -437,13 +511,12 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
 #pragma unroll
     for (int c = 0; c < 7; ++c) fx[c] = fy[c] = R(0);
     if (k >= z0 - 2) {
-      int mir;
-      const int kc = zsource(ph, k + 1, mir);
+      const int jc = k + 1 - (z0 - 2);
       FaceBg<R> bgc;
-      bgc.rho = (R)p.bg_cc[kc];
-      bgc.p = (R)p.bg_cc[ph.nz + kc];
-      bgc.ge = (R)p.bg_cc[2 * ph.nz + kc];
-      bgc.gc = (R)p.bg_cc[3 * ph.nz + kc];
+      bgc.rho = (R)sBc[0][jc];
+      bgc.p = (R)sBc[1][jc];
+      bgc.ge = (R)sBc[2][jc];
+      bgc.gc = (R)sBc[3][jc];
       riemann<R, GR>(xll, xl, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
       const Side<R> yll = side_load<R, GR>(sYR, tdn);
       riemann<R, GR>(yll, yl, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
@@ -474,38 +547,31 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     const R zf_m_l = from_left(zf_m);
     const R ry_l = from_left(ry);
     const R ry_prev_l = from_left(ry_prev);
+    if (!EARLY) load_update();
     R ex_new = 0, ey_new = 0, ez_new = 0;
     if (k >= z0 - 1) {
       // cells of plane k
-      if (k >= z0 && owner) {
-        const size_t q = (size_t)k * plane + colq;
-        double us[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + q];
+      if (upd) {
         double r[5];
 #pragma unroll
         for (int f = 0; f < 5; ++f) r[f] = acc[f] + ((double)fzc[f] - (double)fzp[f]) * ph.idz;
         // sources S - S_hat: gravity on the density deviation, rho g.v,
         // heating, forcing (Sect. 2.1, eq. wb2)
-        double s1 = 0.0, s2 = 0.0, s3 = (us[0] - p.bg_cc[k]) * ph.gz, s4 = us[3] * ph.gz;
-        if (p.heat) s4 += p.heat[k];
+        const int jk = k - (z0 - 2);
+        double s1 = 0.0, s2 = 0.0, s3 = (us[0] - sBc[0][jk]) * ph.gz;
+        double s4 = us[3] * ph.gz + sBc[4][jk];
         if (p.force) {
-          const double f0 = p.force[q], f1 = p.force[ncell + q], f2 = p.force[2 * ncell + q];
-          s1 += us[0] * f0;
-          s2 += us[0] * f1;
-          s3 += us[0] * f2;
-          s4 += us[1] * f0 + us[2] * f1 + us[3] * f2;
+          s1 += us[0] * fo[0];
+          s2 += us[0] * fo[1];
+          s3 += us[0] * fo[2];
+          s4 += us[1] * fo[0] + us[2] * fo[1] + us[3] * fo[2];
         }
         r[1] -= s1;
         r[2] -= s2;
         r[3] -= s3;
         r[4] -= s4;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) {
-          double v = cb * us[f] - cdt * r[f];
-          if (ca != 0.0) v += ca * p.U0[f * ncell + q];
-          p.Uo[f * ncell + q] = v;
-        }
+        for (int f = 0; f < 5; ++f) p.Uo[f * ncell + qc] = cb * us[f] - cdt * r[f] + ca * u0[f];
       }
       // x/y divergence of plane k+1
       R fyc[5];
@@ -539,30 +605,20 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     // ---------------- P4: faces B_x(k), B_y(k), B_z(k+1/2) --------------
     const R ez_r = from_right(ez_cur);
     const R ey_r = from_right(ey_new);
-    if (k >= z0 && owner) {
-      const size_t q = (size_t)k * plane + colq;
+    if (upd) {
       const double ez_u = (double)sEZ[k & 1][tup];
       const double rbx = (ez_u - (double)ez_cur) * ph.idy -
                          ((double)ey_new - (double)ey_prev) * ph.idz;
       const double rby = ((double)ex_new - (double)ex_prev) * ph.idz -
                          ((double)ez_r - (double)ez_cur) * ph.idx;
-      double bx = cb * p.Bxs[q] - cdt * rbx;
-      double by = cb * p.Bys[q] - cdt * rby;
-      if (ca != 0.0) {
-        bx += ca * p.Bx0[q];
-        by += ca * p.By0[q];
-      }
-      p.Bxo[q] = bx;
-      p.Byo[q] = by;
+      p.Bxo[qc] = cb * bxs - cdt * rbx + ca * bx0;
+      p.Byo[qc] = cb * bys - cdt * rby + ca * by0;
     }
-    if (k >= z0 - 1 && k + 1 < z1 && owner && !(ph.reflect && k + 1 == 0)) {
-      const size_t qf = (size_t)(k + 1) * plane + colq;
+    if (updz) {
       const double ex_u = (double)sEX[tup];
       const double rbz = ((double)ey_r - (double)ey_new) * ph.idx -
                          (ex_u - (double)ex_new) * ph.idy;
-      double bz = cb * p.Bzs[qf] - cdt * rbz;
-      if (ca != 0.0) bz += ca * p.Bz0[qf];
-      p.Bzo[qf] = bz;
+      p.Bzo[qfz] = cb * bzf - cdt * rbz + ca * bz0;
     }
 
     // ---------------- shift the pipeline --------------------------------
