@@ -203,9 +203,32 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   c.ncell = (size_t)desc->nx * desc->ny * desc->nz;
   c.nfz = (size_t)desc->nx * desc->ny * ph.nzf;
   // z planes per stage block: a longer segment re-reads fewer halo planes
-  // (4 extra per segment), a shorter one gives more blocks; MHD_ZSEG
-  // overrides the default for tuning
-  c.zseg = 32;
+  // (4 extra per segment), a shorter one gives more blocks.  The blocks run
+  // in rounds of (CUs x resident blocks per CU); pick the segment that
+  // minimises rounds x (planes + 4) over 16..48 planes.  MHD_ZSEG
+  // overrides the choice for tuning.
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    const long long slots = (long long)cus * mhd::stage_blocks_per_cu(c);
+    const long long tiles = (long long)((desc->nx + mhd::TB - 1) / mhd::TB) *
+                            ((desc->ny + mhd::TB - 1) / mhd::TB);
+    const int nz = desc->nz;
+    c.zseg = nz < 16 ? nz : 16;
+    long long best = -1;
+    for (int zs = 16; zs <= 48 && zs <= nz; ++zs) {
+      const int segs = (nz + zs - 1) / zs;
+      const int len = (nz + segs - 1) / segs;  // balanced segments
+      const long long rounds = (tiles * segs + slots - 1) / slots;
+      const long long cost = rounds * (len + 4);
+      if (best < 0 || cost < best) {
+        best = cost;
+        c.zseg = len;
+      }
+    }
+  }
   if (const char *zs = std::getenv("MHD_ZSEG")) {
     const int v = std::atoi(zs);
     if (v >= 1 && v <= mhd::ZSEG_MAX) c.zseg = v;

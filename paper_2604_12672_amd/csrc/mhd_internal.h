@@ -96,6 +96,8 @@ hipError_t launch_diagnostics(const Ctx &c, const double *U, const double *Bx,
                               double *out /* host, 12 */);
 hipError_t launch_zero_walls(const Ctx &c, double *Bz);
 size_t mlp_bytes();
+// resident stage blocks per CU for the context's kernel variant (>= 1)
+int stage_blocks_per_cu(const Ctx &c);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0);
 

@@ -687,6 +687,22 @@ static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b,
                        cc, dt_host, c.zseg);
 }
 
+template <typename R>
+static const void *stage_fn(const Ctx &c) {
+  if (!c.ph.gasrad) return reinterpret_cast<const void *>(&stage_kernel<R, false, false>);
+  if (c.d.eos_guess == MHD_GUESS_MLP)
+    return reinterpret_cast<const void *>(&stage_kernel<R, true, true>);
+  return reinterpret_cast<const void *>(&stage_kernel<R, true, false>);
+}
+
+int stage_blocks_per_cu(const Ctx &c) {
+  const void *f = c.d.precision == MHD_PREC_SPLIT ? stage_fn<float>(c) : stage_fn<double>(c);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, NTHREADS, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
 hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
                         double cc, double dt_host) {
   const Phys &ph = c.ph;
