@@ -351,11 +351,29 @@ struct SideQ {  // derived side quantities
   R F[7];
 };
 
+// Reciprocals of two numbers.  FP64: one hardware reciprocal with its
+// Newton steps serves both (1/a = b/(ab)); FP32: the hardware reciprocal is
+// a single instruction, so each is taken directly.
+template <typename R>
+__device__ __forceinline__ void rcp2(R a, R b, R &ia, R &ib) {
+  if constexpr (sizeof(R) == 8) {
+    const R r = rcp<R>(a * b);
+    ia = b * r;
+    ib = a * r;
+  } else {
+    ia = rcp<R>(a);
+    ib = rcp<R>(b);
+  }
+}
+
+// Side quantities from the reconstructed deviations; ir = 1/rho and
+// igm = 1/(gamma_e - 1) come from the caller (taken for both sides at
+// once).  Returns the fast speed along the normal, c_s^2 and |v|^2.
 template <typename R, bool GR>
-__device__ __forceinline__ void side_prep(const Side<R> &s, R bn,
-                                          const FaceBg<R> &bg, R gam, R igm1,
-                                          SideQ<R> &q, R &cf, R &mach2) {
-  q.rho = bg.rho + s.drho;
+__device__ __forceinline__ void side_prep(const Side<R> &s, R bn, const FaceBg<R> &bg, R rho,
+                                          R ir, R igm, R gam, SideQ<R> &q, R &cf, R &cs2,
+                                          R &v2) {
+  q.rho = rho;
   q.vn = s.vn;
   q.v1 = s.v1;
   q.v2 = s.v2;
@@ -364,26 +382,17 @@ __device__ __forceinline__ void side_prep(const Side<R> &s, R bn,
   const R P = bg.p + s.dp;
   const R bn2 = bn * bn;
   const R B2 = bn2 + s.b1 * s.b1 + s.b2 * s.b2;
-  const R v2 = s.vn * s.vn + s.v1 * s.v1 + s.v2 * s.v2;
-  const R ir = rcp<R>(q.rho);
-  R igm, gc;
-  if (GR) {
-    igm = rcp<R>(bg.ge + s.dge - R(1));
-    gc = bg.gc + s.dgc;
-  } else {
-    igm = igm1;
-    gc = gam;
-  }
+  v2 = s.vn * s.vn + s.v1 * s.v1 + s.v2 * s.v2;
+  const R gc = GR ? bg.gc + s.dgc : gam;
   q.pt = s.dp + R(0.5) * B2;  // p_T - P_hat
-  q.E = P * igm + R(0.5) * q.rho * v2 + R(0.5) * B2;
-  const R cs2 = gc * P * ir;
-  mach2 = v2 * rcp<R>(cs2);
+  q.E = P * igm + R(0.5) * rho * v2 + R(0.5) * B2;
+  cs2 = gc * P * ir;
   const R a2b2 = cs2 + B2 * ir;
-  R disc = a2b2 * a2b2 - R(4) * cs2 * bn2 * ir;
-  disc = disc > R(0) ? disc : R(0);
+  // discriminant clipped at zero against rounding (fmax: also maps NaN to 0)
+  const R disc = fmax(a2b2 * a2b2 - R(4) * cs2 * bn2 * ir, R(0));
   cf = sqroot<R>(R(0.5) * (a2b2 + sqroot<R>(disc)));
   q.vb = s.vn * bn + s.v1 * s.b1 + s.v2 * s.b2;
-  const R rv = q.rho * s.vn;
+  const R rv = rho * s.vn;
   q.F[0] = rv;
   q.F[1] = rv * s.vn + q.pt - bn2;
   q.F[2] = rv * s.v1 - bn * s.b1;
@@ -398,34 +407,29 @@ struct Star {  // single-star state of one side, as differences from U
   R rho, drho;     // rho*, rho* - rho
   R dv1, dv2;      // v*_t - v_t
   R db1, db2;      // B*_t - B_t
-  R dE;            // E* - E
-  R vb;            // v* . B*
+  R isd, dvn;      // 1/(S - S_M), S_M - v_n
 };
 
-// Single-star state of one side (Miyoshi & Kusano 2005), with every
-// difference U* - U written so that no large number is subtracted from
-// another (the split mode depends on it).
+// Density, transverse velocity and field of the single-star state of one
+// side (Miyoshi & Kusano 2005), every difference U* - U written so that no
+// large number is subtracted from another (the split mode depends on it).
+// isd = 1/(S - S_M) comes from the caller; iD = 1/D of a non-degenerate side.
 template <typename R>
-__device__ __forceinline__ void star_side(const SideQ<R> &q, R S, R SM, R pst,
-                                          R bn, R bgp, Star<R> &st) {
-  const R isd = rcp<R>(S - SM);
+__device__ __forceinline__ void star_side(const SideQ<R> &q, R S, R SM, R bn, R isd, R svn,
+                                          bool nondeg, R iD, Star<R> &st) {
   const R f = q.rho * isd;
-  const R svn = S - q.vn, dvn = SM - q.vn;
+  const R dvn = SM - q.vn;
+  st.isd = isd;
+  st.dvn = dvn;
   st.rho = f * svn;
   st.drho = f * dvn;
-  const R D = q.rho * svn * (S - SM) - bn * bn;
-  // degenerate when |D| <= 1e-8 rho (S - v_n)^2: v_t and B_t unchanged
-  const bool nondeg = fabs(D) > R(1e-8) * q.rho * svn * svn;
-  const R iD = rcp<R>(D);
+  // degenerate (|D| <= 1e-8 rho (S - v_n)^2): v_t and B_t unchanged
   const R qv = nondeg ? bn * dvn * iD : R(0);           // v*_t - v_t = -B_t qv
   const R qb = nondeg ? q.rho * svn * dvn * iD : R(0);  // B*_t - B_t = B_t qb
   st.dv1 = -q.b1 * qv;
   st.dv2 = -q.b2 * qv;
   st.db1 = q.b1 * qb;
   st.db2 = q.b2 * qb;
-  st.vb = SM * bn + (q.v1 + st.dv1) * (q.b1 + st.db1) + (q.v2 + st.dv2) * (q.b2 + st.db2);
-  // E* - E = [(S_M - v_n)(E + P_hat) + p~* S_M - p~ v_n + B_n (v.B - v*.B*)] / (S - S_M)
-  st.dE = (dvn * (q.E + bgp) + pst * SM - q.pt * q.vn + bn * (q.vb - st.vb)) * isd;
 }
 
 template <typename R>
@@ -439,38 +443,70 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
                                         R bn, const FaceBg<R> &bg, R gam,
                                         R igm1, int xi_mode, R mcut, R imcut,
                                         R F[7]) {
+  const R rhoL = bg.rho + L.drho, rhoR = bg.rho + Rt.drho;
+  R irL, irR, igL = igm1, igR = igm1;
+  rcp2<R>(rhoL, rhoR, irL, irR);
+  if (GR) rcp2<R>(bg.ge + L.dge - R(1), bg.ge + Rt.dge - R(1), igL, igR);
   SideQ<R> qL, qR;
-  R cfL, cfR, m2L, m2R;
-  side_prep<R, GR>(L, bn, bg, gam, igm1, qL, cfL, m2L);
-  side_prep<R, GR>(Rt, bn, bg, gam, igm1, qR, cfR, m2R);
-  const R cmax = cfL > cfR ? cfL : cfR;
-  const R SL = (qL.vn < qR.vn ? qL.vn : qR.vn) - cmax;
-  const R SR = (qL.vn > qR.vn ? qL.vn : qR.vn) + cmax;
-  const R aL = (SL - qL.vn) * qL.rho, aR = (SR - qR.vn) * qR.rho;
+  R cfL, cfR, csL, csR, v2L, v2R;
+  side_prep<R, GR>(L, bn, bg, rhoL, irL, igL, gam, qL, cfL, csL, v2L);
+  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, igR, gam, qR, cfR, csR, v2R);
+  const R cmax = fmax(cfL, cfR);
+  const R SL = fmin(qL.vn, qR.vn) - cmax;
+  const R SR = fmax(qL.vn, qR.vn) + cmax;
+  const R svnL = SL - qL.vn, svnR = SR - qR.vn;
+  const R aL = svnL * qL.rho, aR = svnR * qR.rho;
   const R iden = rcp<R>(aR - aL);
   const R SM = (aR * qR.vn - aL * qL.vn - qR.pt + qL.pt) * iden;
   // low-dissipation factor xi on the upwind term of p_T* (sonic Mach)
   R xi = R(1);
   if (xi_mode != MHD_XI_OFF) {
-    const R M = sqroot<R>(m2L > m2R ? m2L : m2R);
+    R m2;
+    if constexpr (sizeof(R) == 8) {
+      // max(v_L^2/c_L^2, v_R^2/c_R^2) with one reciprocal
+      m2 = fmax(v2L * csR, v2R * csL) * rcp<R>(csL * csR);
+    } else {
+      m2 = fmax(v2L * rcp<R>(csL), v2R * rcp<R>(csR));
+    }
+    const R M = sqroot<R>(m2);
     if (xi_mode == MHD_XI_LINEAR)
-      xi = M * imcut < R(1) ? M * imcut : R(1);
+      xi = fmin(M * imcut, R(1));
     else
       xi = M < mcut ? M : R(1);
   }
-  const R pst = (aR * qL.pt - aL * qR.pt +
-                 xi * qL.rho * qR.rho * (SR - qR.vn) * (SL - qL.vn) * (qR.vn - qL.vn)) *
+  const R pst = (aR * qL.pt - aL * qR.pt + xi * qL.rho * qR.rho * svnR * svnL * (qR.vn - qL.vn)) *
                 iden;
+  // single-star states of both sides
+  R isdL, isdR;
+  rcp2<R>(SL - SM, SR - SM, isdL, isdR);
+  const R bn2 = bn * bn;
+  const R DL = qL.rho * svnL * (SL - SM) - bn2, DR = qR.rho * svnR * (SR - SM) - bn2;
+  const bool ndL = fabs(DL) > R(1e-8) * qL.rho * svnL * svnL;
+  const bool ndR = fabs(DR) > R(1e-8) * qR.rho * svnR * svnR;
+  R iDL, iDR;
+  rcp2<R>(ndL ? DL : R(1), ndR ? DR : R(1), iDL, iDR);
   Star<R> sL, sR;
-  star_side<R>(qL, SL, SM, pst, bn, bg.p, sL);
-  star_side<R>(qR, SR, SM, pst, bn, bg.p, sR);
+  star_side<R>(qL, SL, SM, bn, isdL, svnL, ndL, iDL, sL);
+  star_side<R>(qR, SR, SM, bn, isdR, svnR, ndR, iDR, sR);
+  // Alfven waves: sqrt(rho*) of both sides, 1/sqrt(rho*) and 1/(sum)
   const R sqL = sqroot<R>(sL.rho), sqR = sqroot<R>(sR.rho);
+  R isqL, isqR, is;
+  if constexpr (sizeof(R) == 8) {
+    const R pr = sqL * sqR, sm = sqL + sqR;
+    const R r = rcp<R>(pr * sm);
+    isqL = sqR * sm * r;
+    isqR = sqL * sm * r;
+    is = pr * r;
+  } else {
+    isqL = rcp<R>(sqL);
+    isqR = rcp<R>(sqR);
+    is = rcp<R>(sqL + sqR);
+  }
   const R abn = fabs(bn);
-  const R SsL = SM - abn * rcp<R>(sqL);
-  const R SsR = SM + abn * rcp<R>(sqR);
-  // double-star transverse velocity and field (Alfven waves)
+  const R SsL = SM - abn * isqL;
+  const R SsR = SM + abn * isqR;
+  // double-star transverse velocity and field
   const R sg = bn >= R(0) ? R(1) : R(-1);
-  const R is = rcp<R>(sqL + sqR);
   const R vL1 = qL.v1 + sL.dv1, vL2 = qL.v2 + sL.dv2, vR1 = qR.v1 + sR.dv1, vR2 = qR.v2 + sR.dv2;
   const R bL1 = qL.b1 + sL.db1, bL2 = qL.b2 + sL.db2, bR1 = qR.b1 + sR.db1, bR2 = qR.b2 + sR.db2;
   const R w1 = (sqL * vL1 + sqR * vR1 + (bR1 - bL1) * sg) * is;
@@ -478,48 +514,50 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   const R c1 = (sqL * bR1 + sqR * bL1 + sqL * sqR * (vR1 - vL1) * sg) * is;
   const R c2 = (sqL * bR2 + sqR * bL2 + sqL * sqR * (vR2 - vL2) * sg) * is;
   const R vbss = SM * bn + w1 * c1 + w2 * c2;
-  // side holding x/t = 0
-  const bool lf = SM >= R(0);
+  // region (eq. flux-hlld): outside the fan, or inside on the side of the
+  // contact that holds x/t = 0, single or double star
+  const bool outL = R(0) <= SL, outR = SR < R(0);
+  const bool lf = outL || (!outR && SM >= R(0));
+  const bool fan = !(outL || outR);
+  const bool dstar = lf ? (SsL < R(0)) : (R(0) <= SsR);
   const R S = sel(lf, SL, SR), Ss = sel(lf, SsL, SsR), sq = sel(lf, sqL, sqR);
   const R rho = sel(lf, qL.rho, qR.rho);
   const R rs = sel(lf, sL.rho, sR.rho), drs = sel(lf, sL.drho, sR.drho);
   const R dv1 = sel(lf, sL.dv1, sR.dv1), dv2 = sel(lf, sL.dv2, sR.dv2);
   const R db1 = sel(lf, sL.db1, sR.db1), db2 = sel(lf, sL.db2, sR.db2);
-  const R dE = sel(lf, sL.dE, sR.dE), vbs = sel(lf, sL.vb, sR.vb);
   const R vs1 = sel(lf, vL1, vR1), vs2 = sel(lf, vL2, vR2);
   const R bs1 = sel(lf, bL1, bR1), bs2 = sel(lf, bL2, bR2);
+  // E* - E of the selected side:
+  // [(S_M - v_n)(E + P_hat) + p~* S_M - p~ v_n + B_n (v.B - v*.B*)] / (S - S_M)
+  const R E = sel(lf, qL.E, qR.E), pt = sel(lf, qL.pt, qR.pt), vn = sel(lf, qL.vn, qR.vn);
+  const R vb = sel(lf, qL.vb, qR.vb), isd = sel(lf, sL.isd, sR.isd);
+  const R dvn = sel(lf, sL.dvn, sR.dvn);
+  const R vbs = SM * bn + vs1 * bs1 + vs2 * bs2;
+  const R dE = (dvn * (E + bg.p) + pst * SM - pt * vn + bn * (vb - vbs)) * isd;
   R Fa[7];
 #pragma unroll
   for (int c = 0; c < 7; ++c) Fa[c] = sel(lf, qL.F[c], qR.F[c]);
   // single-star flux F* = F + S (U* - U); the interface pressure p~*
-  // carries the low-dissipation factor into the normal momentum
-  R Fs[7];
+  // carries the low-dissipation factor into the normal momentum;
+  // double-star flux F** = F* + S* (U** - U*)
+  const R esg = lf ? -sg : sg;
+  R Fs[7], Fss[7];
   Fs[0] = Fa[0] + S * drs;
-  Fs[1] = rs * SM * SM + pst - bn * bn;
+  Fs[1] = rs * SM * SM + pst - bn2;
   Fs[2] = Fa[2] + S * (drs * vs1 + rho * dv1);
   Fs[3] = Fa[3] + S * (drs * vs2 + rho * dv2);
   Fs[4] = Fa[4] + S * dE;
   Fs[5] = Fa[5] + S * db1;
   Fs[6] = Fa[6] + S * db2;
-  // double-star flux F** = F* + S* (U** - U*)
-  const R esg = lf ? -sg : sg;
-  R Fss[7];
-  Fss[0] = Fs[0];
-  Fss[1] = Fs[1];
   Fss[2] = Fs[2] + Ss * rs * (w1 - vs1);
   Fss[3] = Fs[3] + Ss * rs * (w2 - vs2);
   Fss[4] = Fs[4] + Ss * sq * (vbs - vbss) * esg;
   Fss[5] = Fs[5] + Ss * (c1 - bs1);
   Fss[6] = Fs[6] + Ss * (c2 - bs2);
-  // region: outside the fan, single star, double star (eq. flux-hlld)
-  const bool outL = R(0) <= SL, outR = SR < R(0);
-  const bool star1 = lf ? (R(0) <= SsL) : (SsR < R(0));
+  F[0] = fan ? Fs[0] : Fa[0];
+  F[1] = fan ? Fs[1] : Fa[1];
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
-    R v = star1 ? Fs[c] : Fss[c];
-    v = outR ? qR.F[c] : v;
-    F[c] = outL ? qL.F[c] : v;
-  }
+  for (int c = 2; c < 7; ++c) F[c] = fan ? (dstar ? Fss[c] : Fs[c]) : Fa[c];
 }
 
 // ---------------------------------------------------------------------------
