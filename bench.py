@@ -34,11 +34,13 @@ HBM_PEAK_GBS = 8000.0
 # U^(1) (64 B); stage 2 reads U^n and U^(1) and writes U^(n+1): 128 + 192 =
 # 320 B per SSP-RK2 step, 160 B per stage launch on average.  The gas +
 # radiation EOS adds the temperature guess read and the solution written
-# (16 B) when Newton starts from the previous temperature (the learned guess
-# needs no stored temperature); a forcing field adds its three components
+# (16 B) when Newton starts from the previous temperature, or the guess
+# read (8 B) when it starts from the learned guess (written by the guess
+# kernel before the stage); a forcing field adds its three components
 # (24 B).
 BYTES_STATE_STAGE = 160.0
 BYTES_T_STAGE = 16.0
+BYTES_GUESS_STAGE = 8.0
 BYTES_FORCE_STAGE = 24.0
 METRIC = "zone-updates/s (3D MHD 256^3) FP64 vs FP32+learned-EOS; % HBM roofline"
 
@@ -114,8 +116,8 @@ def gpu_run(mhd, w, precision, steps, warmup, mlp=None):
 
 def stage_bytes(w, learned):
     b = BYTES_STATE_STAGE
-    if w.T is not None and not learned:
-        b += BYTES_T_STAGE
+    if w.T is not None:
+        b += BYTES_GUESS_STAGE if learned else BYTES_T_STAGE
     if w.force is not None:
         b += BYTES_FORCE_STAGE
     return b

@@ -139,8 +139,10 @@ int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *force,
    T0 = 10^(y / norm[5] + norm[4]).  Host arrays: w1 [64][2] and b1 [64]
    FP32, w2 [64 out][64 in] and w3 [64] BF16 bit patterns, b2 [64] FP32, b3,
    norm [6].  All three layers run on the matrix cores with FP32
-   accumulation; Newton then polishes in FP64 (at most 8 steps, then the
-   bracketed solve).  Must precede the first step.  Copies the weights. */
+   accumulation, in a guess kernel that fills the context's guess array from
+   the stage input before each stage; the stage then polishes in FP64
+   Newton (at most 8 steps, then the bracketed solve).  Must precede the
+   first step.  Copies the weights. */
 int mhd_set_eos_mlp(mhd_ctx *ctx, const float *w1, const float *b1,
                     const uint16_t *w2, const float *b2, const uint16_t *w3,
                     float b3, const double *norm);

@@ -410,9 +410,14 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.Byo = c.By[o];
     p.Bzo = c.Bz[o];
     const bool prev_t = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T;
-    p.Tin = prev_t ? c.T[c.tcur] : nullptr;
+    const bool learned = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP;
+    if (learned) {
+      // learned guesses of the stage input, polished by Newton in the stage
+      HIPCHK(h, mhd::launch_mlp_guess(c, p.Us, p.Bxs, p.Bys, p.Bzs, c.T[0]));
+    }
+    p.Tin = prev_t ? c.T[c.tcur] : (learned ? c.T[0] : nullptr);
     p.Tout = prev_t ? c.T[1 - c.tcur] : nullptr;
-    p.mlp = c.mlp;
+    p.newton_cap = learned ? c.ph.newton_maxit_mlp : c.ph.newton_maxit;
     p.bg_cc = c.bg_cc;
     p.bg_fz = c.bg_fz;
     p.heat = c.heat;

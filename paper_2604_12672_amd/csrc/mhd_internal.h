@@ -49,7 +49,7 @@ struct StagePtrs {
   const double *bg_cc, *bg_fz;         // [4][nz], [4][nzf]
   const double *heat, *force;          // nullable
   const double *dt_dev;                // device dt (nullable: use dt_host)
-  const void *mlp;                     // packed guess network (MlpLds layout)
+  int newton_cap;                      // Newton steps before the bracketed solve
   int *flags;                          // latched error flags
   unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
 };
@@ -98,6 +98,8 @@ hipError_t launch_zero_walls(const Ctx &c, double *Bz);
 size_t mlp_bytes();
 // resident stage blocks per CU for the context's kernel variant (>= 1)
 int stage_blocks_per_cu(const Ctx &c);
+hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
+                            const double *Bz, double *Tg);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0);
 

@@ -219,23 +219,16 @@ __device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, i
   for (int i = tid; i < (int)(sizeof(MlpLds) / 16); i += nthreads) d4[i] = s4[i];
 }
 
-template <typename R, bool GR, bool ML>
+template <typename R, bool GR>
 __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
     int zseg) {
-  static_assert(!ML || GR, "the learned guess belongs to the gas+radiation EOS");
   static_assert(sizeof(MlpLds) % 16 == 0, "MlpLds is copied in 16-byte words");
   constexpr int NF = Cfg<R, GR>::NF;
-  constexpr bool EARLY = sizeof(R) == 8 || !GR || ML;
+  constexpr bool EARLY = sizeof(R) == 8 || !GR;
   // FP64 runs one wave per SIMD (register-bound): it has the registers to
   // hold the next plane's cell data while it works on the current one
   constexpr bool PREFETCH = sizeof(R) == 8;
-  __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
-  const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
-  if (ML) {
-    stage_mlp(p.mlp, sMlpRaw, threadIdx.x, NTHREADS);
-    __syncthreads();
-  }
   constexpr int NS = NFS_<GR>::v;
   constexpr int LW = TT + 2;  // LDS plane edge: columns -2 .. 15
   constexpr int LP = LW * LW;
@@ -409,18 +402,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       } else {
         load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
       }
-      if (ML) {
-        if (ring && !PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
-        // learned guesses for the own cells (two passes) and for the ring
-        // cells of lanes 0..15 (one pass); every lane takes part
-        float x0, x1, r0 = 0.0f, r1 = 0.0f;
-        mlp_inputs(ph, c.u[0], specific_eint(c.u, c.b), x0, x1);
-        if (ring) mlp_inputs(ph, rc.u[0], specific_eint(rc.u, rc.b), r0, r1);
-        c.tg = mlp_guess_wave(ph, sMlp, x0, x1, lane);
-        const double tr = mlp_guess_low(ph, sMlp, r0, r1, lane);
-        rc.tg = tr;
-      }
-      const int maxit = ML ? ph.newton_maxit_mlp : ph.newton_maxit;
+      const int maxit = p.newton_cap;
       const int jq = q - (z0 - 2);
       const double bgq[4] = {sBc[0][jq], sBc[1][jq], sBc[2][jq], sBc[3][jq]};
       {
@@ -439,7 +421,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         bad |= o.bad;
       }
       if (ring) {
-        if (!ML && !PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        if (!PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
         PrimOut ro;
         R Wr[NF];
         prim_cell<R, GR>(ph, rc, bgq, mir, Wr, ro, maxit);
@@ -677,22 +659,17 @@ static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b,
   const Phys &ph = c.ph;
   dim3 block(NTHREADS);
   if (!ph.gasrad)
-    hipLaunchKernelGGL((stage_kernel<R, false, false>), grid, block, 0, c.stream, ph, p, a, b,
-                       cc, dt_host, c.zseg);
-  else if (c.d.eos_guess == MHD_GUESS_MLP)
-    hipLaunchKernelGGL((stage_kernel<R, true, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
+    hipLaunchKernelGGL((stage_kernel<R, false>), grid, block, 0, c.stream, ph, p, a, b, cc,
                        dt_host, c.zseg);
   else
-    hipLaunchKernelGGL((stage_kernel<R, true, false>), grid, block, 0, c.stream, ph, p, a, b,
-                       cc, dt_host, c.zseg);
+    hipLaunchKernelGGL((stage_kernel<R, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
+                       dt_host, c.zseg);
 }
 
 template <typename R>
 static const void *stage_fn(const Ctx &c) {
-  if (!c.ph.gasrad) return reinterpret_cast<const void *>(&stage_kernel<R, false, false>);
-  if (c.d.eos_guess == MHD_GUESS_MLP)
-    return reinterpret_cast<const void *>(&stage_kernel<R, true, true>);
-  return reinterpret_cast<const void *>(&stage_kernel<R, true, false>);
+  if (!c.ph.gasrad) return reinterpret_cast<const void *>(&stage_kernel<R, false>);
+  return reinterpret_cast<const void *>(&stage_kernel<R, true>);
 }
 
 int stage_blocks_per_cu(const Ctx &c) {
@@ -879,6 +856,57 @@ hipError_t launch_init_temperature(const Ctx &c, const double *U,
   nb = nb < 4096 ? nb : 4096;
   hipLaunchKernelGGL(init_temperature_kernel, dim3(nb), dim3(256), 0, c.stream, c.ph, U, Bx, By,
                      Bz, Tg, T, c.flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// learned initial guess of every cell of a state (before each stage in the
+// learned mode): the stage kernel reads it as its temperature guess
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *__restrict__ U,
+                                                        const double *__restrict__ Bx,
+                                                        const double *__restrict__ By,
+                                                        const double *__restrict__ Bz,
+                                                        const void *mlp,
+                                                        double *__restrict__ Tg) {
+  __shared__ __attribute__((aligned(16))) char sMlpRaw[sizeof(MlpLds)];
+  const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
+  stage_mlp(mlp, sMlpRaw, threadIdx.x, 256);
+  __syncthreads();
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t n = plane * ph.nz;
+  const int lane = threadIdx.x & 63;
+  // every lane of a wave runs the matrix passes; lanes past the end repeat
+  // the last cell and store nothing
+  for (size_t base = (size_t)blockIdx.x * 256; base < n; base += (size_t)gridDim.x * 256) {
+    const bool valid = base + threadIdx.x < n;
+    const size_t q = valid ? base + threadIdx.x : n - 1;
+    const int i = (int)(q % ph.nx);
+    const int j = (int)((q / ph.nx) % ph.ny);
+    const int k = (int)(q / plane);
+    const int ip = i + 1 == ph.nx ? 0 : i + 1;
+    const int jp = j + 1 == ph.ny ? 0 : j + 1;
+    const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
+    double u[5], b[3];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) u[f] = U[f * n + q];
+    b[0] = 0.5 * (Bx[q] + Bx[q - i + ip]);
+    b[1] = 0.5 * (By[q] + By[q + (size_t)(jp - j) * ph.nx]);
+    b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
+    float x0, x1;
+    mlp_inputs(ph, u[0], specific_eint(u, b), x0, x1);
+    const double t = mlp_guess_wave(ph, sMlp, x0, x1, lane);
+    if (valid) Tg[q] = t;
+  }
+}
+
+hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
+                            const double *Bz, double *Tg) {
+  long long nb = (long long)((c.ncell + 255) / 256);
+  nb = nb < 8192 ? nb : 8192;
+  hipLaunchKernelGGL(mlp_guess_kernel, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph, U, Bx,
+                     By, Bz, c.mlp, Tg);
   return hipGetLastError();
 }
 
