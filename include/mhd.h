@@ -152,7 +152,10 @@ int mhd_set_eos_mlp(mhd_ctx *ctx, const float *w1, const float *b1,
    (MHD_GUESS_PREV_T: T_guess[i], or the bracketed solve when T_guess is
    NULL; MHD_GUESS_MLP: the learned guess).  T0 (nullable) receives the
    guess used.  stats (nullable) = {Newton steps, largest count, bracketed
-   solves}.  All pointers are device memory; synchronises. */
+   solves}.  All pointers are device memory.  With stats the call
+   synchronises and returns latched device errors; without, it is
+   asynchronous on the context stream (errors surface at the next
+   synchronising call). */
 int mhd_eos_solve(mhd_ctx *ctx, const double *rho, const double *e,
                   const double *T_guess, int64_t n, double *T, double *T0,
                   int64_t stats[3]);

@@ -189,6 +189,7 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   ph.rmu = ph.gasrad ? desc->rgas / desc->mu : 0.0;
   ph.arad = ph.gasrad ? desc->arad : 0.0;
   ph.cg = ph.gasrad ? desc->rgas / ((desc->gamma - 1.0) * desc->mu) : 0.0;
+  ph.icg = ph.cg > 0.0 ? 1.0 / ph.cg : 0.0;
   ph.gz = desc->grav[2];
   ph.newton_tol = desc->newton_tol;
   ph.newton_maxit = desc->newton_maxit;
@@ -612,12 +613,11 @@ int mhd_eos_solve(mhd_ctx *h, const double *rho, const double *e, const double *
   HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
   HIPCHK(h, mhd::launch_eos_solve(c, rho, e, c.d.eos_guess == MHD_GUESS_MLP ? nullptr : T_guess,
                                   (long long)n, T, T0));
-  if (stats) {
-    unsigned long long st[3];
-    HIPCHK(h, hipMemcpyAsync(st, c.nstats, sizeof(st), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(h, hipStreamSynchronize(c.stream));
-    for (int i = 0; i < 3; ++i) stats[i] = (int64_t)st[i];
-  }
+  if (!stats) return MHD_OK;  // asynchronous: errors surface at the next sync
+  unsigned long long st[3];
+  HIPCHK(h, hipMemcpyAsync(st, c.nstats, sizeof(st), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(h, hipStreamSynchronize(c.stream));
+  for (int i = 0; i < 3; ++i) stats[i] = (int64_t)st[i];
   return latched(h);
 }
 

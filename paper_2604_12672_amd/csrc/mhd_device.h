@@ -65,7 +65,9 @@ __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
                                                double e, double tguess, int maxit,
                                                double &T, int &iters,
                                                int &fallback) {
-  const double cg = ph.cg, ar = ph.arad / rho, tol = ph.newton_tol * e;
+  // the Newton step divides by c_v > 0 with the refined reciprocal (a few
+  // ulp); the stopping test on |de| decides the result's accuracy
+  const double cg = ph.cg, ar = ph.arad * rcp<double>(rho), tol = ph.newton_tol * e;
   iters = 0;
   fallback = 0;
   double t = tguess;
@@ -78,14 +80,15 @@ __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
         iters = n;
         return 0;
       }
-      t = t + de / (cg + 4.0 * ar * t3);
+      t = t + de * rcp<double>(cg + 4.0 * ar * t3);
       iters = n + 1;
       if (!(t > 0.0 && t < INFINITY)) break;
     }
   }
   fallback = 1;
-  double lo = fmin(e / (2.0 * cg), sqrt(sqrt(e / (2.0 * ar))));
-  double hi = fmin(e / cg, sqrt(sqrt(e / ar)));
+  const double ecg = e * ph.icg, ear = e * rcp<double>(ar);
+  double lo = fmin(0.5 * ecg, sqroot<double>(sqroot<double>(0.5 * ear)));
+  double hi = fmin(ecg, sqroot<double>(sqroot<double>(ear)));
   t = 0.5 * (lo + hi);
   for (int n = 0; n < 400; ++n) {
     const double t3 = t * t * t;
@@ -98,7 +101,7 @@ __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
       lo = t;
     else
       hi = t;
-    const double tn = t + de / (cg + 4.0 * ar * t3);
+    const double tn = t + de * rcp<double>(cg + 4.0 * ar * t3);
     t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
     if (hi - lo <= 8.881784197001252e-16 * hi) {
       T = t;

@@ -28,6 +28,7 @@ struct Phys {
   double dx, dy, dz, idx, idy, idz;
   double gamma, gm1, igm1;
   double rmu, arad, cg;  // R/mu, a, C_g = R/((gamma-1) mu)
+  double icg;            // 1 / C_g
   double gz;
   double newton_tol;
   int newton_maxit;

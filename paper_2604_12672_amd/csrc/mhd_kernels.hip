@@ -879,21 +879,39 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
   const int lane = threadIdx.x & 63;
   // every lane of a wave runs the matrix passes; lanes past the end repeat
   // the last cell and store nothing
-  for (size_t base = (size_t)blockIdx.x * 256; base < n; base += (size_t)gridDim.x * 256) {
-    const bool valid = base + threadIdx.x < n;
-    const size_t q = valid ? base + threadIdx.x : n - 1;
+  // cell data of one cell: U and the six faces (the next cell's data is
+  // requested before this one is evaluated)
+  auto fetch = [&](size_t q, double u[5], double f[6]) {
     const int i = (int)(q % ph.nx);
     const int j = (int)((q / ph.nx) % ph.ny);
     const int k = (int)(q / plane);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
     const int jp = j + 1 == ph.ny ? 0 : j + 1;
     const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) u[c] = U[c * n + q];
+    f[0] = Bx[q];
+    f[1] = Bx[q - i + ip];
+    f[2] = By[q];
+    f[3] = By[q + (size_t)(jp - j) * ph.nx];
+    f[4] = Bz[q];
+    f[5] = Bz[(size_t)kp * plane + (q - (size_t)k * plane)];
+  };
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t base = (size_t)blockIdx.x * 256;
+  double un[5] = {1, 0, 0, 0, 1}, fn[6] = {0, 0, 0, 0, 0, 0};
+  if (base < n) fetch(base + threadIdx.x < n ? base + threadIdx.x : n - 1, un, fn);
+  for (; base < n; base += stride) {
+    const bool valid = base + threadIdx.x < n;
+    const size_t q = valid ? base + threadIdx.x : n - 1;
     double u[5], b[3];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = U[f * n + q];
-    b[0] = 0.5 * (Bx[q] + Bx[q - i + ip]);
-    b[1] = 0.5 * (By[q] + By[q + (size_t)(jp - j) * ph.nx]);
-    b[2] = 0.5 * (Bz[q] + Bz[(size_t)kp * plane + (q - (size_t)k * plane)]);
+    for (int c = 0; c < 5; ++c) u[c] = un[c];
+    b[0] = 0.5 * (fn[0] + fn[1]);
+    b[1] = 0.5 * (fn[2] + fn[3]);
+    b[2] = 0.5 * (fn[4] + fn[5]);
+    if (base + stride < n)
+      fetch(base + stride + threadIdx.x < n ? base + stride + threadIdx.x : n - 1, un, fn);
     float x0, x1;
     mlp_inputs(ph, u[0], specific_eint(u, b), x0, x1);
     const double t = mlp_guess_wave(ph, sMlp, x0, x1, lane);
@@ -929,12 +947,28 @@ __global__ __launch_bounds__(256) void eos_solve_kernel(
   const int lane = threadIdx.x & 63;
   unsigned long long it = 0, mx = 0, fb = 0;
   int bad = 0;
-  for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
-       base += (long long)gridDim.x * blockDim.x) {
+  // the next sample's inputs are requested before this one is solved
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long base = (long long)blockIdx.x * blockDim.x;
+  double rn = 0.0, en = 0.0, gn = NAN;
+  if (base < n) {
+    const long long q0 = base + threadIdx.x < n ? base + threadIdx.x : n - 1;
+    rn = rho[q0];
+    en = e[q0];
+    if (tguess) gn = tguess[q0];
+  }
+  for (; base < n; base += stride) {
     const bool valid = base + threadIdx.x < n;
     const long long q = valid ? base + threadIdx.x : n - 1;
-    const double r = rho[q], ee = e[q];
-    double g = tguess ? tguess[q] : NAN;
+    const double r = rn, ee = en;
+    double g = gn;
+    if (base + stride < n) {
+      const long long qn =
+          base + stride + threadIdx.x < n ? base + stride + threadIdx.x : n - 1;
+      rn = rho[qn];
+      en = e[qn];
+      if (tguess) gn = tguess[qn];
+    }
     if (ML) {
       float x0, x1;
       mlp_inputs(ph, r, ee, x0, x1);

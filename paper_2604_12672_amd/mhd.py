@@ -222,18 +222,19 @@ class Grid:
         self._check(self._L.mhd_set_eos_mlp(self._h, p(w1), p(b1), p(w2), p(b2), p(w3),
                                             C.c_float(b3), p(norm)))
 
-    def eos_solve(self, rho, e, T_guess=None, with_guess=False):
+    def eos_solve(self, rho, e, T_guess=None, with_guess=False, stats=True, out=None):
         """Invert T(rho, e) on the device for torch CUDA float64 tensors.
-        Returns (T, T0 or None, (newton steps, max steps, bracketed solves))."""
+        Returns (T, T0 or None, (newton steps, max steps, bracketed solves)
+        or None).  stats=False makes the call asynchronous."""
         import torch
         n = rho.numel()
-        T = torch.empty_like(rho)
+        T = torch.empty_like(rho) if out is None else out
         T0 = torch.empty_like(rho) if with_guess else None
-        st = (C.c_int64 * 3)()
+        st = (C.c_int64 * 3)() if stats else None
         self._check(self._L.mhd_eos_solve(self._h, _ptr(rho, DEVICE), _ptr(e, DEVICE),
                                           _ptr(T_guess, DEVICE), n, _ptr(T, DEVICE),
                                           _ptr(T0, DEVICE), st))
-        return T, T0, tuple(st)
+        return T, T0, (tuple(st) if stats else None)
 
     def set_state(self, U, Bx, By, Bz, T=None):
         w = _where(U, Bx, By, Bz, T)

@@ -125,3 +125,23 @@ def test_learned_guess_requires_weights(mhd):
         g.step(1e-4)
     assert e.value.code == -6
     g.close()
+
+
+def test_async_batch_solve_matches_synchronous(mhd, model):
+    """Without statistics the batch inversion is asynchronous on the
+    library's stream and gives the same temperatures."""
+    import torch
+    p = wl.gasrad_params(4, 4, 4)
+    rho, e, T = eos_mlp.sample(p, 30_001, seed=23)
+    r, ee = torch.from_numpy(rho).cuda(), torch.from_numpy(e).cuda()
+    for guess in (mhd.GUESS_MLP, mhd.GUESS_PREV_T):
+        g = mhd.Grid(p, eos_guess=guess)
+        if guess == mhd.GUESS_MLP:
+            g.set_eos_mlp(model)
+        Ts, _, st = g.eos_solve(r, ee)
+        Ta, _, none = g.eos_solve(r, ee, stats=False)
+        g.sync()
+        g.close()
+        assert none is None and st is not None
+        assert torch.equal(Ts, Ta)
+        np.testing.assert_allclose(Ta.cpu().numpy(), T, rtol=1.01e-11)
