@@ -114,16 +114,16 @@ __device__ __forceinline__ int eos_temperature(const Phys &ph, double rho,
 
 // P, and the auxiliary indices gamma_e = P/(rho e) + 1, gamma_c = rho c_s^2/P
 // with c_s^2 = (dP/drho)_T + T (dP/dT)_rho^2 / (rho^2 c_v).
-__device__ __forceinline__ void eos_thermo(const Phys &ph, double rho, double e,
+__device__ __forceinline__ void eos_thermo(const Phys &ph, double rho, double ir, double e,
                                            double T, double &P, double &ge,
                                            double &gc) {
   const double t3 = T * T * T;
   P = rho * ph.rmu * T + ph.arad * t3 * T * (1.0 / 3.0);
-  const double cv = ph.cg + 4.0 * ph.arad * t3 / rho;
+  const double cv = ph.cg + 4.0 * ph.arad * t3 * ir;
   const double dpdt = rho * ph.rmu + (4.0 / 3.0) * ph.arad * t3;
-  const double cs2 = ph.rmu * T + T * dpdt * dpdt / (rho * rho * cv);
-  ge = P / (rho * e) + 1.0;
-  gc = rho * cs2 / P;
+  const double cs2 = ph.rmu * T + T * dpdt * dpdt * (ir * ir) * rcp<double>(cv);
+  ge = P * ir * rcp<double>(e) + 1.0;
+  gc = rho * cs2 * rcp<double>(P);
 }
 
 // ---------------------------------------------------------------------------
@@ -143,7 +143,7 @@ struct PrimOut {
 // specific internal energy e_int = (E - rho v^2/2 - B_cc^2/2) / rho
 __device__ __forceinline__ double specific_eint(const double u[5], const double b[3]) {
   const double rho = u[0];
-  const double ir = 1.0 / rho;
+  const double ir = rcp<double>(rho);
   const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
   const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
   return (u[4] - 0.5 * rho * (vx * vx + vy * vy + vz * vz) - 0.5 * b2) * ir;
@@ -157,7 +157,7 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
                                           const double bg[4], PrimOut &o,
                                           int maxit = -1) {
   const double rho = u[0];
-  const double ir = 1.0 / rho;
+  const double ir = rcp<double>(rho);
   const double vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
   const double e = specific_eint(u, b);
   o.bad = (rho > 0.0 && e > 0.0 && e < INFINITY) ? 0 : 1;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
         o.bad = 2;
     }
     o.T = T;
-    eos_thermo(ph, rho, e, T, P, ge, gc);
+    eos_thermo(ph, rho, ir, e, T, P, ge, gc);
   } else {
     P = ph.gm1 * rho * e;
   }
@@ -324,7 +324,15 @@ __device__ __forceinline__ double mlp_guess_low(const Phys &ph, const MlpLds &S,
 template <typename R>
 __device__ __forceinline__ R vanleer(R a, R b) {
   const R ab = a * b;
-  return ab > R(0) ? R(2) * ab * rcp<R>(a + b) : R(0);
+  if constexpr (sizeof(R) == 4) {
+    // branch-free (a + b is nonzero whenever ab > 0, the only case used)
+    const R q = R(2) * ab * rcp<R>(a + b);
+    return ab > R(0) ? q : R(0);
+  } else {
+    // FP64: the reciprocal sequence only where a lane needs it (keeps the
+    // register pressure of the unrolled reconstruction down)
+    return ab > R(0) ? R(2) * ab * rcp<R>(a + b) : R(0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +584,9 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
 
 template <typename R>
 __device__ __forceinline__ R upwind(R m, R up, R dn) {
-  return m > R(0) ? up : (m < R(0) ? dn : R(0.5) * (up + dn));
+  const R mid = R(0.5) * (up + dn);  // branch-free selection
+  const R side = m > R(0) ? up : dn;
+  return m == R(0) ? mid : side;
 }
 
 template <typename R>
