@@ -80,7 +80,7 @@ extern "C" {
 typedef struct mhd_ctx mhd_ctx; /* opaque */
 
 typedef struct {
-  int32_t nx, ny, nz;     /* interior cells, each >= 1                         */
+  int32_t nx, ny, nz;     /* interior cells, each >= 1; nx ny (nz+1) < 2^32    */
   double lo[3], hi[3];    /* box corners, hi > lo                              */
   int32_t bc[3];          /* bc[0] = bc[1] = MHD_BC_PERIODIC;
                              bc[2] = MHD_BC_PERIODIC or MHD_BC_REFLECT        */

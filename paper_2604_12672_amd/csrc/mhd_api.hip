@@ -49,6 +49,10 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "nx, ny, nz must be >= 1";
     return MHD_ERR_ARG;
   }
+  if ((double)d->nx * d->ny * (d->nz + 1.0) >= 4294967296.0) {
+    msg = "grid too large: nx ny (nz+1) must stay below 2^32 cells";
+    return MHD_ERR_ARG;
+  }
   const double cells = (double)d->nx * d->ny * d->nz;
   if (cells > 4.0e9) {
     msg = "grid too large";
@@ -609,10 +613,12 @@ int mhd_eos_solve(mhd_ctx *h, const double *rho, const double *e, const double *
   if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   if (n == 0) return MHD_OK;
-  HIPCHK(h, hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream));
-  HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
+  if (stats) {
+    HIPCHK(h, hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream));
+    HIPCHK(h, hipMemsetAsync(c.flags, 0, sizeof(int), c.stream));
+  }
   HIPCHK(h, mhd::launch_eos_solve(c, rho, e, c.d.eos_guess == MHD_GUESS_MLP ? nullptr : T_guess,
-                                  (long long)n, T, T0));
+                                  (long long)n, T, T0, stats != nullptr));
   if (!stats) return MHD_OK;  // asynchronous: errors surface at the next sync
   unsigned long long st[3];
   HIPCHK(h, hipMemcpyAsync(st, c.nstats, sizeof(st), hipMemcpyDeviceToHost, c.stream));

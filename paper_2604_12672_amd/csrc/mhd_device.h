@@ -201,8 +201,8 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
 // operand of the next (rows = hidden units, columns = cells).  Layer 1 folds
 // its bias into K = 8 rows (x0h, x0h, x0l, x1h | x1h, x1l, 1, 1) against
 // (w0h, w0l, w0h, w1h | w1l, w1h, b1h, b1l): hi/lo BF16 pairs keep about 16
-// bits of the inputs and of W1, b1.  Layer 3 is a 32-row MFMA whose row 0
-// is W3.
+// bits of the inputs and of W1, b1.  Layer 3 (64 -> 1) takes BF16 dot
+// products of the layer-2 registers with W3 pairs on the vector unit.
 // ---------------------------------------------------------------------------
 
 typedef short v4s __attribute__((ext_vector_type(4)));
@@ -228,9 +228,18 @@ __device__ __forceinline__ v4s pack_bf16(float a, float b, float c, float d) {
   return r;
 }
 
+// ReLU on packed BF16: a negative BF16 is a negative 16-bit integer, so an
+// integer max with 0 clears it (v_pk_max_i16, two values per instruction).
+typedef short v2s __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ v4s relu_bf16(v4s x) { return __builtin_elementwise_max(x, (v4s)0); }
+__device__ __forceinline__ v4s pack_relu(const v16f &d, int j) {
+  return relu_bf16(pack_bf16(d[4 * j], d[4 * j + 1], d[4 * j + 2], d[4 * j + 3]));
+}
+
 // One pass over the 32 cells held by lanes 0..31 (lanes l and l+32 carry
-// the inputs of cell l%32).  Returns the network output on lanes 0..31.
-// Must be called by all 64 lanes.
+// the inputs of cell l%32).  Returns the network output (without b3) of
+// cell l%32 on every lane.  Must be called by all 64 lanes.
 __device__ __forceinline__ float mlp_pass(const MlpLds &S, float x0, float x1, int lane) {
   const float x0h = bf16_round(x0), x1h = bf16_round(x1);
   const v4s b = lane < 32 ? pack_bf16(x0h, x0h, x0 - x0h, x1h)
@@ -241,10 +250,8 @@ __device__ __forceinline__ float mlp_pass(const MlpLds &S, float x0, float x1, i
   v4s h[8];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    h[j] = pack_bf16(fmaxf(c0[4 * j], 0.f), fmaxf(c0[4 * j + 1], 0.f), fmaxf(c0[4 * j + 2], 0.f),
-                     fmaxf(c0[4 * j + 3], 0.f));
-    h[4 + j] = pack_bf16(fmaxf(c1[4 * j], 0.f), fmaxf(c1[4 * j + 1], 0.f),
-                         fmaxf(c1[4 * j + 2], 0.f), fmaxf(c1[4 * j + 3], 0.f));
+    h[j] = pack_relu(c0, j);
+    h[4 + j] = pack_relu(c1, j);
   }
   v16f d0, d1;
 #pragma unroll
@@ -257,26 +264,24 @@ __device__ __forceinline__ float mlp_pass(const MlpLds &S, float x0, float x1, i
     d0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[0][kb][lane], h[kb], d0, 0, 0, 0);
     d1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[1][kb][lane], h[kb], d1, 0, 0, 0);
   }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    h[j] = pack_bf16(fmaxf(d0[4 * j], 0.f), fmaxf(d0[4 * j + 1], 0.f), fmaxf(d0[4 * j + 2], 0.f),
-                     fmaxf(d0[4 * j + 3], 0.f));
-    h[4 + j] = pack_bf16(fmaxf(d1[4 * j], 0.f), fmaxf(d1[4 * j + 1], 0.f),
-                         fmaxf(d1[4 * j + 2], 0.f), fmaxf(d1[4 * j + 3], 0.f));
-  }
-  v16f e = {};
-  const bool col0 = (lane & 31) == 0;
+  // layer 3, 64 -> 1: this lane holds hidden units 8j + 4(l/32) + t (d0)
+  // and 32 + the same (d1) of its cell; BF16 dot products of register pairs
+  // with the matching W3 pairs, then the other half of the wave's rows
   const int kh = 4 * (lane >> 5);
+  float y = 0.0f;
 #pragma unroll
-  for (int kb = 0; kb < 8; ++kb) {
-    v4s a;
-    a[0] = col0 ? S.w3[8 * kb + kh] : (short)0;
-    a[1] = col0 ? S.w3[8 * kb + kh + 1] : (short)0;
-    a[2] = col0 ? S.w3[8 * kb + kh + 2] : (short)0;
-    a[3] = col0 ? S.w3[8 * kb + kh + 3] : (short)0;
-    e = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, h[kb], e, 0, 0, 0);
+  for (int j = 0; j < 8; ++j) {
+    const v4s hj = j < 4 ? pack_relu(d0, j) : pack_relu(d1, j - 4);
+    const int row = (j < 4 ? 8 * j : 32 + 8 * (j - 4)) + kh;
+    const v2s wlo = *reinterpret_cast<const v2s *>(&S.w3[row]);
+    const v2s whi = *reinterpret_cast<const v2s *>(&S.w3[row + 2]);
+    const v2s hlo = {hj[0], hj[1]}, hhi = {hj[2], hj[3]};
+    y = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, hlo),
+                                        __builtin_bit_cast(v2bf, wlo), y, false);
+    y = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(v2bf, hhi),
+                                        __builtin_bit_cast(v2bf, whi), y, false);
   }
-  return e[0];
+  return y + __shfl_xor(y, 32);
 }
 
 // Network inputs of one cell: normalised log10 rho and log10 e, clipped to
@@ -305,17 +310,9 @@ __device__ __forceinline__ double mlp_guess_wave(const Phys &ph, const MlpLds &S
   const bool lo = lane < 32;
   const float y0 = mlp_pass(S, lo ? x0 : o0, lo ? x1 : o1, lane);  // cells 0..31
   const float y1 = mlp_pass(S, lo ? o0 : x0, lo ? o1 : x1, lane);  // cells 32..63
-  const float y1x = __shfl_xor(y1, 32);
-  return mlp_temperature(ph, lo ? y0 : y1x);
+  return mlp_temperature(ph, lo ? y0 : y1);
 }
 
-// Guess for the cells held by lanes 0..31 only (one pass).
-__device__ __forceinline__ double mlp_guess_low(const Phys &ph, const MlpLds &S, float x0,
-                                                float x1, int lane) {
-  const float o0 = __shfl_xor(x0, 32), o1 = __shfl_xor(x1, 32);
-  const bool lo = lane < 32;
-  return mlp_temperature(ph, mlp_pass(S, lo ? x0 : o0, lo ? x1 : o1, lane));
-}
 
 // ---------------------------------------------------------------------------
 // reconstruction (Sect. 2.5): van Leer slope, harmonic form

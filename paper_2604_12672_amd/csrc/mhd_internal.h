@@ -102,6 +102,7 @@ int stage_blocks_per_cu(const Ctx &c);
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
                             const double *Bz, double *Tg);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
-                            const double *tguess, long long n, double *T, double *T0);
+                            const double *tguess, long long n, double *T, double *T0,
+                            bool stats);
 
 }  // namespace mhd

@@ -68,6 +68,16 @@ __device__ __forceinline__ int zface(const Phys &ph, int f) {
   return ph.reflect ? f : wrapi(f, ph.nz);
 }
 
+// (i, j, k) of a linear cell index q < nx ny nz (< 2^32: three state
+// copies of a larger grid would not fit in HBM), with 32-bit divisions
+__device__ __forceinline__ void cell_ijk(const Phys &ph, size_t q, int &i, int &j, int &k) {
+  const unsigned u = (unsigned)q, nx = (unsigned)ph.nx, ny = (unsigned)ph.ny;
+  const unsigned r = u / nx;
+  i = (int)(u - r * nx);
+  k = (int)(r / ny);
+  j = (int)(r - (unsigned)k * ny);
+}
+
 struct CellLoad {
   double u[5];
   double b[3];
@@ -721,9 +731,8 @@ __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
        base += (size_t)gridDim.x * blockDim.x) {
     const bool valid = base + threadIdx.x < n;
     const size_t q = valid ? base + threadIdx.x : n - 1;
-    const int i = (int)(q % ph.nx);
-    const int j = (int)((q / ph.nx) % ph.ny);
-    const int k = (int)(q / plane);
+    int i, j, k;
+    cell_ijk(ph, q, i, j, k);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
     const int jp = j + 1 == ph.ny ? 0 : j + 1;
     const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
@@ -830,9 +839,8 @@ __global__ void init_temperature_kernel(Phys ph, const double *__restrict__ U,
   const size_t n = plane * ph.nz;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % ph.nx);
-    const int j = (int)((q / ph.nx) % ph.ny);
-    const int k = (int)(q / plane);
+    int i, j, k;
+    cell_ijk(ph, q, i, j, k);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
     const int jp = j + 1 == ph.ny ? 0 : j + 1;
     const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
@@ -882,9 +890,8 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
   // cell data of one cell: U and the six faces (the next cell's data is
   // requested before this one is evaluated)
   auto fetch = [&](size_t q, double u[5], double f[6]) {
-    const int i = (int)(q % ph.nx);
-    const int j = (int)((q / ph.nx) % ph.ny);
-    const int k = (int)(q / plane);
+    int i, j, k;
+    cell_ijk(ph, q, i, j, k);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
     const int jp = j + 1 == ph.ny ? 0 : j + 1;
     const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);
@@ -988,30 +995,48 @@ __global__ __launch_bounds__(256) void eos_solve_kernel(
     fb += fallback;
     bad |= rc ? 2 : 0;
   }
+  if (bad) atomicOr(flags, bad);
+  if (!stats) return;  // block-uniform: no statistics requested
+  // statistics: wave, then block totals, one set of atomics per block
   for (int o = 32; o > 0; o >>= 1) {
     it += __shfl_xor(it, o);
     fb += __shfl_xor(fb, o);
     const unsigned long long m2 = __shfl_xor(mx, o);
     mx = m2 > mx ? m2 : mx;
   }
+  __shared__ unsigned long long s_st[3][4];
+  const int wv = threadIdx.x >> 6;
   if (lane == 0) {
-    atomicAdd(&stats[0], it);
-    atomicMax(&stats[1], mx);
-    atomicAdd(&stats[2], fb);
+    s_st[0][wv] = it;
+    s_st[1][wv] = mx;
+    s_st[2][wv] = fb;
   }
-  if (bad) atomicOr(flags, bad);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, m = 0, f = 0;
+    for (int w = 0; w < 4; ++w) {
+      a += s_st[0][w];
+      m = s_st[1][w] > m ? s_st[1][w] : m;
+      f += s_st[2][w];
+    }
+    atomicAdd(&stats[0], a);
+    atomicMax(&stats[1], m);
+    atomicAdd(&stats[2], f);
+  }
 }
 
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
-                            const double *tguess, long long n, double *T, double *T0) {
+                            const double *tguess, long long n, double *T, double *T0,
+                            bool stats) {
   long long nb = (n + 255) / 256;
   nb = nb < 8192 ? nb : 8192;
+  unsigned long long *st = stats ? c.nstats : nullptr;
   if (c.d.eos_guess == MHD_GUESS_MLP)
     hipLaunchKernelGGL(eos_solve_kernel<true>, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph,
-                       rho, e, tguess, n, c.mlp, T, T0, c.nstats, c.flags);
+                       rho, e, tguess, n, c.mlp, T, T0, st, c.flags);
   else
     hipLaunchKernelGGL(eos_solve_kernel<false>, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph,
-                       rho, e, tguess, n, c.mlp, T, T0, c.nstats, c.flags);
+                       rho, e, tguess, n, c.mlp, T, T0, st, c.flags);
   return hipGetLastError();
 }
 
@@ -1034,9 +1059,8 @@ __global__ __launch_bounds__(256) void diag_kernel(Phys ph, const double *__rest
   for (int f = 0; f < NDIAG; ++f) v[f] = 0.0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % ph.nx);
-    const int j = (int)((q / ph.nx) % ph.ny);
-    const int k = (int)(q / plane);
+    int i, j, k;
+    cell_ijk(ph, q, i, j, k);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
     const int jp = j + 1 == ph.ny ? 0 : j + 1;
     const int kp = ph.reflect ? k + 1 : (k + 1 == ph.nz ? 0 : k + 1);

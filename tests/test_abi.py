@@ -81,6 +81,7 @@ def _desc(**kw):
     dict(nx=0), dict(nz=-3), dict(gamma=1.0), dict(bcz=7), dict(rk_order=4),
     dict(eos=5), dict(hi=(1.0, 0.0, 1.0)), dict(bcz=1, nz=1),
     dict(eos=1, rgas=0.0), dict(xi_mode=9), dict(mach_cut=0.0),
+    dict(nx=2048, ny=2048, nz=1024),
 ])
 def test_descriptor_validation(lib, bad):
     d = _desc(**bad)
