@@ -53,7 +53,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "caaef8f9d822d98c": {"fp64": (1368092.9, 1059482.8), "split": (1707388.5, 1159491.2)},
+    "9d0f79beb78dff51": {"fp64": (1473385.4, 1105572.9), "split": (1816550.3, 1220551.9)},
 }
 
 
@@ -370,15 +370,20 @@ def main():
         log("bench: gas+radiation box 256^3")
         wg = wl.config(3)
         g64 = gpu_run(mhd, wg, mhd.PREC_FP64, args.steps, args.warmup)
+        gsp = gpu_run(mhd, wg, mhd.PREC_SPLIT, args.steps, args.warmup)
         gml = gpu_run(mhd, wg, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
         gas = {"fp64_prev_t": dict(summary(wg, g64, "gasrad_fp64"), **newton_stats(wg, g64["diag"])),
+               "split_prev_t": dict(summary(wg, gsp, "gasrad_split"), **newton_stats(wg, gsp["diag"])),
                "split_learned": dict(summary(wg, gml, "gasrad_split_learned"),
                                      **newton_stats(wg, gml["diag"])),
                "speedup_split_learned_vs_fp64": round(g64["ms"] / gml["ms"], 3),
+               "learned_guess_kernel": "one MFMA guess kernel per stage (reads U and B, "
+                                       "writes the guess array the stage reads)",
                "workload": "gas+radiation box 256^3, log-uniform rho in [1e-2, 1e2] and "
                            "T in [1e5, 1e8] K, beta 1e6, periodic"}
         out["gasrad"] = gas
-        log(f"bench: gasrad fp64 {g64['ms']:.3f} ms/step, split+learned {gml['ms']:.3f} ms/step")
+        log(f"bench: gasrad fp64 {g64['ms']:.3f} ms/step, split {gsp['ms']:.3f}, "
+            f"split+learned {gml['ms']:.3f} ms/step")
         del wg
         log("bench: batch EOS inversion")
         out["eos_solve"] = eos_bench(mhd, model, args.eos_n)
