@@ -14,7 +14,7 @@
  *   2. the deviation Delta W = W - W_hat from the background (Sect. 2.8);
  *   3. ghost cells: periodic copies, or mirror images at a reflecting wall
  *      (normal velocity and normal field odd, everything else even);
- *   4. per face: van Leer reconstruction of Delta W (Sect. 2.5), the
+ *   4. per face: van Leer or PPH reconstruction of Delta W (Sect. 2.5), the
  *      background added back at the face, the HLLD/LHLLD flux (Sect. 2.6),
  *      and the equilibrium flux F_hat = F(W_hat_f, W_hat_f) subtracted
  *      (eq. wb1);
@@ -194,6 +194,17 @@ double orc_vanleer(double a, double b) {
   double ab = a * b;
   if (ab > 0.0) return 2.0 * ab / (a + b);
   return 0.0;
+}
+
+/* READING: the paper's PPH reconstructs every primitive except the mass
+   fractions with an unlimited parabola on the three-cell stencil (q = 1);
+   without species that is the parabola whose averages over the cells
+   i-1, i, i+1 are the cell values, evaluated at the two faces of cell i:
+   w(i+1/2) = (-w_{i-1} + 5 w_i + 2 w_{i+1}) / 6,
+   w(i-1/2) = (2 w_{i-1} + 5 w_i - w_{i+1}) / 6. */
+void orc_pph(double wm, double wc, double wp, double *lo, double *hi) {
+  *hi = (-wm + 5.0 * wc + 2.0 * wp) / 6.0;
+  *lo = (2.0 * wm + 5.0 * wc - wp) / 6.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -617,10 +628,16 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
           double WL[9], WR[9];
           for (int m = 0; m < 9; ++m) {
             const double *a = dW + (size_t)fl[m] * G;
-            double sL = orc_vanleer(a[pL] - a[pL - st], a[pR] - a[pL]);
-            double sR = orc_vanleer(a[pR] - a[pL], a[pR + st] - a[pR]);
-            WL[m] = a[pL] + 0.5 * sL; /* Delta W_{i-1/2, L} */
-            WR[m] = a[pR] - 0.5 * sR; /* Delta W_{i-1/2, R} */
+            if (c->recon == ORC_RECON_PPH) {
+              double unused;
+              orc_pph(a[pL - st], a[pL], a[pR], &unused, &WL[m]);
+              orc_pph(a[pL], a[pR], a[pR + st], &WR[m], &unused);
+            } else {
+              double sL = orc_vanleer(a[pL] - a[pL - st], a[pR] - a[pL]);
+              double sR = orc_vanleer(a[pR] - a[pL], a[pR + st] - a[pR]);
+              WL[m] = a[pL] + 0.5 * sL; /* Delta W_{i-1/2, L} */
+              WR[m] = a[pR] - 0.5 * sR; /* Delta W_{i-1/2, R} */
+            }
           }
           /* background at the face added back (Sect. 2.8) */
           double bh[4];

@@ -39,6 +39,12 @@ extern "C" {
 #define ORC_XI_STEP 1    /* xi = max(M_L,M_R) if that is < M_cut, else 1    */
 #define ORC_XI_OFF 2     /* xi = 1: plain HLLD                              */
 
+/* reconstruction of the face states (Sect. 2.5) */
+#define ORC_RECON_VANLEER 0 /* linear, van Leer limited slope                  */
+#define ORC_RECON_PPH 1     /* piecewise parabolic (PPH without species): the
+                               unlimited third-order parabola of the three-cell
+                               stencil                                        */
+
 typedef struct {
   int nx, ny, nz;
   double dx, dy, dz;
@@ -52,6 +58,7 @@ typedef struct {
   int newton_maxit;      /* Newton iterations before the bracketed solve   */
   double mach_cut;       /* Mach threshold of the low-dissipation factor   */
   int xi_mode;           /* ORC_XI_*                                        */
+  int recon;             /* ORC_RECON_*                                     */
   const double *bg_cc;   /* [4][nz]  background rho, P, gamma_e, gamma_c at
                             cell centres, or NULL for a zero background     */
   const double *bg_fz;   /* [4][nzf] the same at z faces (NULL with bg_cc)  */
@@ -72,6 +79,10 @@ int orc_eos_invert(const orc_cfg *c, double rho, double eint, double Tguess,
 
 /* Van Leer limited slope from the two one-sided differences (Sect. 2.5). */
 double orc_vanleer(double a, double b);
+
+/* PPH face values of a cell from its own and its neighbours' averages
+   (Sect. 2.5): lo = value at the lower face, hi = at the upper face. */
+void orc_pph(double wm, double wc, double wp, double *lo, double *hi);
 
 /* HLLD / LHLLD interface flux (Sect. 2.6, eq. flux-hlld) in the face frame.
    W = {rho, v_n, v_t1, v_t2, P, B_t1, B_t2, gamma_e, gamma_c};

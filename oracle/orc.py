@@ -18,6 +18,7 @@ _lib = None
 BC_PERIODIC, BC_REFLECT = 0, 1
 EOS_IDEAL, EOS_GASRAD = 0, 1
 XI_LINEAR, XI_STEP, XI_OFF = 0, 1, 2
+RECON_VANLEER, RECON_PPH = 0, 1
 
 _DP = C.POINTER(C.c_double)
 
@@ -31,7 +32,7 @@ class _Cfg(C.Structure):
         ("arad", C.c_double), ("gz", C.c_double),
         ("rk_order", C.c_int), ("newton_tol", C.c_double),
         ("newton_maxit", C.c_int), ("mach_cut", C.c_double),
-        ("xi_mode", C.c_int),
+        ("xi_mode", C.c_int), ("recon", C.c_int),
         ("bg_cc", _DP), ("bg_fz", _DP), ("heat", _DP), ("force", _DP),
     ]
 
@@ -58,6 +59,8 @@ def lib():
         L.orc_eos_thermo.argtypes = [C.POINTER(_Cfg), C.c_double, C.c_double,
                                      _DP, _DP, _DP, _DP]
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
+        L.orc_pph.argtypes = [C.c_double, C.c_double, C.c_double, _DP, _DP]
+        L.orc_pph.restype = None
         L.orc_vanleer.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
     return _lib
@@ -82,7 +85,7 @@ def _check(rc, what):
 DEFAULTS = dict(
     bcz=BC_PERIODIC, eos=EOS_IDEAL, gamma=5.0 / 3.0, mu=0.6, rgas=0.0, arad=0.0,
     gz=0.0, rk_order=2, newton_tol=1e-11, newton_maxit=50, mach_cut=0.6,
-    xi_mode=XI_LINEAR,
+    xi_mode=XI_LINEAR, recon=RECON_VANLEER,
 )
 
 
@@ -108,7 +111,7 @@ class Oracle:
             int(p["bcz"]), int(p["eos"]), float(p["gamma"]), float(p["mu"]),
             float(p["rgas"]), float(p["arad"]), float(p["gz"]), int(p["rk_order"]),
             float(p["newton_tol"]), int(p["newton_maxit"]), float(p["mach_cut"]),
-            int(p["xi_mode"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
+            int(p["xi_mode"]), int(p["recon"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
         )
 
     # -- state helpers -------------------------------------------------
@@ -185,6 +188,13 @@ class Oracle:
 
 def vanleer(a: float, b: float) -> float:
     return lib().orc_vanleer(float(a), float(b))
+
+
+def pph(wm: float, wc: float, wp: float):
+    """(lower, upper) face values of the PPH parabola of a cell."""
+    lo, hi = C.c_double(), C.c_double()
+    lib().orc_pph(float(wm), float(wc), float(wp), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
 
 
 def num_threads() -> int:
