@@ -74,6 +74,11 @@ extern "C" {
 #define MHD_XI_STEP 1     /* xi = max(M_L, M_R) if below mach_cut, else 1   */
 #define MHD_XI_OFF 2      /* xi = 1 (plain HLLD)                            */
 
+#define MHD_RECON_VANLEER 0 /* linear, van Leer limited slope (Sect. 2.5)       */
+#define MHD_RECON_PPH 1     /* piecewise parabolic: the unlimited parabola of the
+                               three-cell stencil (Sect. 2.5, PPH without
+                               species)                                        */
+
 #define MHD_HOST 0
 #define MHD_DEVICE 1
 
@@ -95,6 +100,7 @@ typedef struct {
   int32_t newton_maxit;   /* Newton steps before the bracketed solve           */
   double mach_cut;        /* Mach threshold of the LHLLD factor (paper: 0.6)   */
   int32_t xi_mode;        /* MHD_XI_*                                          */
+  int32_t recon;          /* MHD_RECON_*                                       */
 } mhd_grid_desc;
 
 typedef struct {

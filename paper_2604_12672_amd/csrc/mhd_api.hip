@@ -105,6 +105,10 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "unknown precision";
     return MHD_ERR_ARG;
   }
+  if (d->recon != MHD_RECON_VANLEER && d->recon != MHD_RECON_PPH) {
+    msg = "recon must be MHD_RECON_VANLEER or MHD_RECON_PPH";
+    return MHD_ERR_ARG;
+  }
   if (d->eos_guess != MHD_GUESS_PREV_T && d->eos_guess != MHD_GUESS_MLP) {
     msg = "unknown eos_guess";
     return MHD_ERR_ARG;
@@ -198,6 +202,7 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   ph.newton_tol = desc->newton_tol;
   ph.newton_maxit = desc->newton_maxit;
   ph.xi_mode = desc->xi_mode;
+  ph.recon = desc->recon;
   ph.mach_cut = desc->mach_cut;
   ph.imach_cut = desc->mach_cut > 0.0 ? 1.0 / desc->mach_cut : 0.0;
   ph.dims_active[0] = desc->nx > 1;

@@ -33,6 +33,7 @@ struct Phys {
   double newton_tol;
   int newton_maxit;
   int xi_mode;
+  int recon;  // MHD_RECON_*
   double mach_cut, imach_cut;
   int dims_active[3];  // axis has more than one cell
   int newton_maxit_mlp;  // Newton cap after the learned guess

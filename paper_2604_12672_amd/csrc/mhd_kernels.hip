@@ -134,19 +134,28 @@ struct NFS_ {
   static constexpr int v = GR ? 9 : 7;
 };
 
-// Van Leer reconstruction of one cell along `axis` (0 x, 1 y, 2 z) from its
-// two neighbours: the cell's lower-face value lo (R state of face i-1/2) and
-// upper-face value hi (L state of face i+1/2), in the face frame of the
-// axis (n = axis, t1 = axis+1, t2 = axis+2).
+// Reconstruction of one cell along `axis` (0 x, 1 y, 2 z) from its two
+// neighbours (Sect. 2.5): the cell's lower-face value lo (R state of face
+// i-1/2) and upper-face value hi (L state of face i+1/2), in the face frame
+// of the axis (n = axis, t1 = axis+1, t2 = axis+2).  Van Leer: limited
+// linear slope; PPH: the unlimited parabola whose averages over the three
+// cells are the cell values, lo = (2 m + 5 c - p)/6, hi = (-m + 5 c + 2 p)/6.
 template <typename R, bool GR>
 __device__ __forceinline__ void recon_cell(int axis, const R *m, const R *c,
-                                           const R *p, Side<R> &lo, Side<R> &hi) {
+                                           const R *p, Side<R> &lo, Side<R> &hi,
+                                           bool pph) {
   const int vn = Q_VX + axis, v1 = Q_VX + (axis + 1) % 3, v2 = Q_VX + (axis + 2) % 3;
   const int b1 = Q_BX + (axis + 1) % 3, b2 = Q_BX + (axis + 2) % 3;
   auto rec = [&](int f, R &l, R &h) {
-    const R s = R(0.5) * vanleer<R>(c[f] - m[f], p[f] - c[f]);
-    l = c[f] - s;
-    h = c[f] + s;
+    if (pph) {
+      const R sixth = R(1.0 / 6.0);
+      l = (R(2) * m[f] + R(5) * c[f] - p[f]) * sixth;
+      h = (R(5) * c[f] - m[f] + R(2) * p[f]) * sixth;
+    } else {
+      const R s = R(0.5) * vanleer<R>(c[f] - m[f], p[f] - c[f]);
+      l = c[f] - s;
+      h = c[f] + s;
+    }
   };
   rec(Q_RHO, lo.drho, hi.drho);
   rec(vn, lo.vn, hi.vn);
@@ -326,6 +335,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   const double cdt = cc * dt;
   const R gam = (R)ph.gamma, igm1 = (R)ph.igm1;
   const R mcut = (R)ph.mach_cut, imcut = (R)ph.imach_cut;
+  const bool pph = ph.recon == MHD_RECON_PPH;
 
   // own column state carried along z
   R Wc[NF];        // cell k+1
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       }
       if (k >= z0 - 2) {
         Side<R> botn, topn;
-        recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn);
+        recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn, pph);
         if (k >= z0 - 1) {
           const int fzi = zface(ph, k + 1);
           FaceBg<R> bgf;
@@ -480,7 +490,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           b[f] = sWc[f * LP + lw_own + 1];
         }
         Side<R> xh;
-        recon_cell<R, GR>(0, a, Wc, b, xl, xh);
+        recon_cell<R, GR>(0, a, Wc, b, xl, xh, pph);
         xll = side_from_left<R>(xh);  // L state of the x-face ci-1/2
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -488,7 +498,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           b[f] = sWc[f * LP + lw_own + LW];
         }
         Side<R> yh;
-        recon_cell<R, GR>(1, a, Wc, b, yl, yh);
+        recon_cell<R, GR>(1, a, Wc, b, yl, yh, pph);
         side_store<R, GR>(sYR, tid, yh);
         // cell reference EMF -(v x B) of plane k+1
         rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmhd.so")
 HOST, DEVICE = 0, 1
 PREC_FP64, PREC_SPLIT = 0, 1
 GUESS_PREV_T, GUESS_MLP = 0, 1
+RECON_VANLEER, RECON_PPH = 0, 1
 BC_PERIODIC, BC_REFLECT = 0, 1
 
 ERRORS = {-1: "MHD_ERR_ARG", -2: "MHD_ERR_NO_DEVICE", -3: "MHD_ERR_HIP",
@@ -40,7 +41,7 @@ class GridDesc(C.Structure):
         ("rgas", C.c_double), ("arad", C.c_double), ("grav", C.c_double * 3),
         ("rk_order", C.c_int32), ("precision", C.c_int32), ("eos_guess", C.c_int32),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("mach_cut", C.c_double),
-        ("xi_mode", C.c_int32),
+        ("xi_mode", C.c_int32), ("recon", C.c_int32),
     ]
 
 
@@ -119,6 +120,7 @@ def make_desc(params: dict, precision=PREC_FP64, eos_guess=GUESS_PREV_T) -> Grid
     d.newton_maxit = int(p.get("newton_maxit", 50))
     d.mach_cut = float(p.get("mach_cut", 0.6))
     d.xi_mode = int(p.get("xi_mode", 0))
+    d.recon = int(p.get("recon", RECON_VANLEER))
     return d
 
 
