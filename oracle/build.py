@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "mhd_oracle.c")
+SRCS = [os.path.join(HERE, f) for f in ("mhd_oracle.c", "mhd_diffusion.c")]
 LIB = os.path.join(HERE, "libmhd_oracle.so")
 
 
@@ -18,7 +18,7 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas",
-        SRC, "-o", LIB + ".tmp", "-lm",
+        *SRCS, "-o", LIB + ".tmp", "-lm",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -121,6 +121,36 @@ int orc_primitives(const orc_cfg *c, const double *U, const double *Bx,
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
 int orc_num_threads(void);
 
+/* ------------------------------------------------------------------ */
+/* Thermal diffusion and RKL2 super-time-stepping (Sect. 2.10),        */
+/* mhd_diffusion.c                                                     */
+/* ------------------------------------------------------------------ */
+
+/* opacity law kappa = kappa0 rho^alpha T^beta; clight = speed of light in
+   code units (the conductivity is K = (4 a c / 3) chi, chi = T^3/(kappa rho)) */
+typedef struct {
+  double kappa0, alpha, beta, clight;
+} orc_opacity;
+
+#define ORC_DIFF_EINT 0 /* evolve e_int, EOS inversion every stage          */
+#define ORC_DIFF_TEMP 1 /* evolve T with c_v frozen at the start            */
+
+/* M[T] = (1/rho) div(K grad T) per cell (rho, T, M: [nz][ny][nx]) */
+int orc_diffusion_rhs(const orc_cfg *c, const orc_opacity *op, const double *rho,
+                      const double *T, double *M);
+/* parabolic limit dt_p = 1 / (2 max sum_s D / dx_s^2), D = 4 a c T^3 / (3 kappa rho^2 c_v) */
+int orc_parabolic_dt(const orc_cfg *c, const orc_opacity *op, const double *rho,
+                     const double *T, double *dtp);
+/* number of RKL2 stages for a step dt_h: max(1 + floor((sqrt(9 + 16 dt_h/dt_p) - 1)/2), 3) */
+int orc_rkl2_nsts(double dt_h, double dt_p);
+/* RKL2 coefficients (mu, nu, mu~, gamma~) of stage j of s */
+void orc_rkl2_coeffs(int s, int j, double *mu, double *nu, double *mut, double *gamt);
+/* One RKL2 step of thermal diffusion over dt with nsts stages (mode
+   ORC_DIFF_*); updates E in U and T (in: guess, out: new temperature). */
+int orc_diffuse(const orc_cfg *c, const orc_opacity *op, double *U, const double *Bx,
+                const double *By, const double *Bz, double *T, double dt, int nsts,
+                int mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,15 @@ class _Cfg(C.Structure):
     ]
 
 
+class _Opacity(C.Structure):
+    _fields_ = [("kappa0", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
+                ("clight", C.c_double)]
+
+
+DIFF_EINT, DIFF_TEMP = 0, 1
+C_LIGHT_CODE = 2.99792458e10 / 1e8  # speed of light in units of 1e8 cm/s
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -61,6 +70,14 @@ def lib():
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_pph.argtypes = [C.c_double, C.c_double, C.c_double, _DP, _DP]
         L.orc_pph.restype = None
+        OP = C.POINTER(_Opacity)
+        L.orc_diffusion_rhs.argtypes = [C.POINTER(_Cfg), OP, _DP, _DP, _DP]
+        L.orc_parabolic_dt.argtypes = [C.POINTER(_Cfg), OP, _DP, _DP, _DP]
+        L.orc_rkl2_nsts.argtypes = [C.c_double, C.c_double]
+        L.orc_rkl2_coeffs.argtypes = [C.c_int, C.c_int, _DP, _DP, _DP, _DP]
+        L.orc_rkl2_coeffs.restype = None
+        L.orc_diffuse.argtypes = [C.POINTER(_Cfg), OP, _DP, _DP, _DP, _DP, _DP, C.c_double,
+                                  C.c_int, C.c_int]
         L.orc_vanleer.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
     return _lib
@@ -140,6 +157,30 @@ class Oracle:
                                   _ptr(RBz)), "orc_residual")
         return RU, RBx, RBy, RBz, Tout
 
+    # -- thermal diffusion (Sect. 2.10) ----------------------------------
+    def diffuse(self, st: dict, dt: float, nsts: int, op, mode=DIFF_EINT) -> None:
+        """One RKL2 step of thermal diffusion; updates st["U"][4] and st["T"]."""
+        U, Bx, By, Bz, T = self._state(st)
+        _check(lib().orc_diffuse(C.byref(self.cfg), C.byref(op), _ptr(U), _ptr(Bx), _ptr(By),
+                                 _ptr(Bz), _ptr(T), float(dt), int(nsts), int(mode)),
+               "orc_diffuse")
+
+    def diffusion_rhs(self, rho, T, op):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        M = np.empty_like(T)
+        _check(lib().orc_diffusion_rhs(C.byref(self.cfg), C.byref(op), _ptr(rho), _ptr(T),
+                                       _ptr(M)), "orc_diffusion_rhs")
+        return M
+
+    def parabolic_dt(self, rho, T, op) -> float:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        out = C.c_double(0.0)
+        _check(lib().orc_parabolic_dt(C.byref(self.cfg), C.byref(op), _ptr(rho), _ptr(T),
+                                      C.byref(out)), "orc_parabolic_dt")
+        return out.value
+
     def compute_dt(self, st: dict, cfl: float) -> float:
         U, Bx, By, Bz, T = self._state(st)
         out = C.c_double(0.0)
@@ -184,6 +225,22 @@ class Oracle:
         lib().orc_eos_thermo(C.byref(self.cfg), float(rho), float(T), C.byref(P), C.byref(e),
                              C.byref(cv), C.byref(cs2))
         return P.value, e.value, cv.value, cs2.value
+
+
+def opacity(kappa0, alpha=0.0, beta=0.0, clight=C_LIGHT_CODE):
+    """Opacity law kappa = kappa0 rho^alpha T^beta (thermal diffusion)."""
+    return _Opacity(float(kappa0), float(alpha), float(beta), float(clight))
+
+
+def rkl2_nsts(dt_h: float, dt_p: float) -> int:
+    return lib().orc_rkl2_nsts(float(dt_h), float(dt_p))
+
+
+def rkl2_coeffs(s: int, j: int):
+    """(mu, nu, mu~, gamma~) of stage j of an s-stage RKL2 step."""
+    v = [C.c_double() for _ in range(4)]
+    lib().orc_rkl2_coeffs(int(s), int(j), *[C.byref(x) for x in v])
+    return tuple(x.value for x in v)
 
 
 def vanleer(a: float, b: float) -> float:
