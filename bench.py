@@ -237,6 +237,57 @@ def split_error(mhd, n, steps):
             "reference": "FP64 GPU path (oracle-matched), same dt sequence"}
 
 
+# algorithmic bytes per cell of one RKL2 stage: reads y_(j-1), y_(j-2), y_0,
+# M_0, rho, T and chi of the previous stage (7 x 8 B), writes y_j, T, chi
+# (3 x 8 B); the temperature form also reads c_v0
+BYTES_RKL2_STAGE = {0: 80.0, 1: 88.0}
+
+
+def rkl2_bench(mhd, n):
+    """One RKL2 super step of thermal diffusion on the gas+radiation box
+    (n^3) with a Kramers-like opacity, dt = 100 parabolic limits (the
+    paper's stage count for that ratio); time per stage from HIP events
+    around the asynchronous call, in both forms."""
+    import torch
+    from paper_2604_12672_amd import workloads as wl
+    w = wl.config(3, n)
+    res = {}
+    for name, mode in (("eint", mhd.DIFF_EINT), ("temp", mhd.DIFF_TEMP)):
+        g = mhd.Grid(w.params)
+        g.load(w)
+        g.set_opacity(0.2, alpha=1.0, beta=-3.5)
+        dtp = g.parabolic_dt()
+        dt = 100.0 * dtp
+        s = g.diffuse(dt, 0, mode)  # warm-up, allocation, stage count
+        g.sync()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            g.diffuse(dt, s, mode)
+        e1.record(stream)
+        e1.synchronize()
+        g.sync()
+        ms = e0.elapsed_time(e1) / reps
+        g.close()
+        stage_ms = ms / s
+        achieved = BYTES_RKL2_STAGE[mode] * w.ncells / (stage_ms * 1e-3) / 1e9
+        res[name] = {"stages": s, "ms_per_super_step": round(ms, 4),
+                     "ms_per_stage": round(stage_ms, 4),
+                     "cell_stages_per_s": round(w.ncells / (stage_ms * 1e-3), 1),
+                     "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                                  "kernel": "diff_stage_kernel",
+                                  "bytes_per_cell_stage": BYTES_RKL2_STAGE[mode]}}
+        log(f"bench: rkl2 {name}: {s} stages, {ms:.3f} ms per super step")
+    res["workload"] = (f"gas+radiation box {n}^3, kappa = 0.2 rho T^-3.5, one RKL2 super "
+                       f"step of 100 parabolic limits")
+    return res
+
+
 def cpu_baseline(n, target_s=12.0):
     """The FP64 oracle on the host cores: the same stratified-box workload at
     n^3, as many steps as fit in about target_s seconds (at least one)."""
@@ -420,6 +471,8 @@ def main():
         out["turbulence"] = t
         log(f"bench: turbulence {tr['ms']:.3f} ms/step, divB {tr['diag']['divb_max']:.2e}")
         del wt
+    if not args.no_extras and not args.only:
+        out["rkl2_diffusion"] = rkl2_bench(mhd, args.n)
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle) {args.cpu_n}^3")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)

@@ -79,6 +79,9 @@ extern "C" {
                                three-cell stencil (Sect. 2.5, PPH without
                                species)                                        */
 
+#define MHD_DIFF_EINT 0 /* thermal diffusion evolves e_int (EOS every stage)  */
+#define MHD_DIFF_TEMP 1 /* evolves T with c_v frozen at the start (Sect. 2.10) */
+
 #define MHD_HOST 0
 #define MHD_DEVICE 1
 
@@ -197,6 +200,29 @@ int mhd_sync(mhd_ctx *ctx);
 
 /* div B (eq. divb), conservation totals, Newton statistics (synchronises). */
 int mhd_diagnostics(mhd_ctx *ctx, mhd_diag *out);
+
+/* ---- thermal diffusion with RKL2 super-time-stepping (Sect. 2.10) ---- */
+
+/* Opacity law kappa = kappa0 rho^alpha T^beta (a stand-in for the paper's
+   tabulated or fitted opacities) and the speed of light in code units;
+   the face conductivity is (4 a c / 3) times the harmonic mean of
+   chi = T^3 / (kappa rho).  Gas+radiation EOS only; kappa0, clight > 0. */
+int mhd_set_opacity(mhd_ctx *ctx, double kappa0, double alpha, double beta,
+                    double clight);
+
+/* Parabolic stability limit dt_p = 1 / (2 max sum_s D / dx_s^2),
+   D = 4 a c T^3 / (3 kappa rho^2 c_v), of the current state (synchronises). */
+int mhd_parabolic_dt(mhd_ctx *ctx, double *dtp_out);
+
+/* One RKL2 step of rho de_int/dt = div(K grad T) over dt (density, velocity
+   and field fixed; E changes by rho (e_new - e_old)), with nsts stages, or
+   when nsts <= 0 the paper's count max(1 + floor((sqrt(9 + 16 dt/dt_p) -
+   1)/2), 3) (that computes dt_p and synchronises).  mode MHD_DIFF_*.
+   *nsts_used (nullable) receives the stage count.  Reflecting z walls are
+   insulating.  Asynchronous otherwise; errors latch as for mhd_step.  The
+   work arrays (10 doubles per cell) are allocated on the first call. */
+int mhd_diffuse(mhd_ctx *ctx, double dt, int32_t nsts, int32_t mode,
+                int32_t *nsts_used);
 
 /* Message of the last failed call on this context ("" if none); a message
    for a failed mhd_init_grid is returned for ctx == NULL. */

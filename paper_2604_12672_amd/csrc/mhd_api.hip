@@ -317,6 +317,15 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.flags);
   (void)hipFree(c.nstats);
   (void)hipFree(c.mlp);
+  mhd::DiffBufs &d = c.diff;
+  (void)hipFree(d.e0);
+  for (int i = 0; i < 4; ++i) (void)hipFree(d.y[i]);
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(d.T[i]);
+    (void)hipFree(d.chi[i]);
+  }
+  (void)hipFree(d.M0);
+  (void)hipFree(d.cv0);
   delete h;
   return MHD_OK;
 }
@@ -630,6 +639,107 @@ int mhd_eos_solve(mhd_ctx *h, const double *rho, const double *e, const double *
   HIPCHK(h, hipStreamSynchronize(c.stream));
   for (int i = 0; i < 3; ++i) stats[i] = (int64_t)st[i];
   return latched(h);
+}
+
+int mhd_set_opacity(mhd_ctx *h, double kappa0, double alpha, double beta, double clight) {
+  if (!h) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.ph.gasrad) return fail(h, MHD_ERR_ARG, "thermal diffusion needs the gas+radiation EOS");
+  if (!(kappa0 > 0.0) || !(clight > 0.0) || !std::isfinite(alpha) || !std::isfinite(beta) ||
+      !std::isfinite(kappa0) || !std::isfinite(clight))
+    return fail(h, MHD_ERR_ARG, "kappa0 and clight must be finite and > 0");
+  c.dparams.pref = 4.0 * c.ph.arad * clight / 3.0;
+  c.dparams.alpha = alpha;
+  c.dparams.beta = beta;
+  c.dparams.ikappa0 = 1.0 / kappa0;
+  c.have_opacity = true;
+  return MHD_OK;
+}
+
+static int diffusion_ready(mhd_ctx *h) {
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "diffusion before mhd_set_state");
+  if (!c.have_opacity) return fail(h, MHD_ERR_STATE, "mhd_set_opacity not called");
+  return MHD_OK;
+}
+
+int mhd_parabolic_dt(mhd_ctx *h, double *dtp_out) {
+  if (!h || !dtp_out) return MHD_ERR_ARG;
+  if (int rc = diffusion_ready(h)) return rc;
+  mhd::Ctx &c = h->c;
+  const int s = c.cur;
+  const double *Tg = c.d.eos_guess == MHD_GUESS_PREV_T ? c.T[c.tcur] : nullptr;
+  double *slot = c.red + c.red_len - 1;
+  HIPCHK(h, mhd::launch_parabolic_dt(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg, slot));
+  double dtp = 0.0;
+  HIPCHK(h, hipMemcpyAsync(&dtp, slot, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  if (int rc = latched(h)) return rc;
+  if (!(dtp > 0.0)) return fail(h, MHD_ERR_UNPHYSICAL, "parabolic limit is not positive");
+  *dtp_out = dtp;
+  return MHD_OK;
+}
+
+// RKL2 stage coefficients (Meyer, Balsara & Aslam): b_0 = b_1 = b_2 = 1/3,
+// b_j = (j^2 + j - 2) / (2 j (j + 1)); w1 = 4 / (s^2 + s - 2); stage 1:
+// mu~ = b_1 w1; stage j >= 2: mu = (2j - 1)/j b_j / b_{j-1},
+// nu = -(j - 1)/j b_j / b_{j-2}, mu~ = mu w1, gamma~ = -(1 - b_{j-1}) mu~.
+static double rkl2_b(int j) { return j <= 2 ? 1.0 / 3.0 : (j * (double)j + j - 2.0) / (2.0 * j * (j + 1.0)); }
+
+int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts_used) {
+  if (!h) return MHD_ERR_ARG;
+  if (int rc = diffusion_ready(h)) return rc;
+  mhd::Ctx &c = h->c;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, MHD_ERR_ARG, "dt must be finite and > 0");
+  if (mode != MHD_DIFF_EINT && mode != MHD_DIFF_TEMP) return fail(h, MHD_ERR_ARG, "bad mode");
+  if (nsts > 100000) return fail(h, MHD_ERR_ARG, "nsts too large");
+  mhd::DiffBufs &d = c.diff;
+  if (!d.e0) {
+    const size_t bytes = sizeof(double) * c.ncell;
+    HIPCHK(h, hipMalloc(&d.e0, bytes));
+    for (int i = 0; i < 4; ++i) HIPCHK(h, hipMalloc(&d.y[i], bytes));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(h, hipMalloc(&d.T[i], bytes));
+      HIPCHK(h, hipMalloc(&d.chi[i], bytes));
+    }
+    HIPCHK(h, hipMalloc(&d.M0, bytes));
+    HIPCHK(h, hipMalloc(&d.cv0, bytes));
+  }
+  if (nsts <= 0) {
+    double dtp;
+    if (int rc = mhd_parabolic_dt(h, &dtp)) return rc;
+    const int n = 1 + (int)std::floor(0.5 * (std::sqrt(9.0 + 16.0 * dt / dtp) - 1.0));
+    if (n > 100000) return fail(h, MHD_ERR_ARG, "dt needs more than 100000 stages");
+    nsts = n > 3 ? n : 3;
+  }
+  if (nsts_used) *nsts_used = nsts;
+  const int s = c.cur;
+  const int tform = mode == MHD_DIFF_TEMP;
+  const bool prev_t = c.d.eos_guess == MHD_GUESS_PREV_T;
+  const double *Tg = prev_t ? c.T[c.tcur] : nullptr;
+  HIPCHK(h, mhd::launch_diff_init(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg, tform));
+  const double *y0 = tform ? d.y[3] : d.e0;
+  const double *p1 = y0, *p2 = y0;
+  const double w1 = 4.0 / ((double)nsts * nsts + nsts - 2.0);
+  int ta = 0;
+  for (int j = 1; j <= nsts; ++j) {
+    double mu = 0.0, nu = 0.0, mut, gamt = 0.0;
+    if (j == 1) {
+      mut = rkl2_b(1) * w1;
+    } else {
+      mu = (2.0 * j - 1.0) / j * rkl2_b(j) / rkl2_b(j - 1);
+      nu = -(j - 1.0) / j * rkl2_b(j) / rkl2_b(j - 2);
+      mut = mu * w1;
+      gamt = -(1.0 - rkl2_b(j - 1)) * mut;
+    }
+    double *out = d.y[(j - 1) % 3];
+    HIPCHK(h, mhd::launch_diff_stage(c, c.U[s], ta, y0, p1, p2, out, tform, j == 1, mu, nu,
+                                     mut, gamt, dt));
+    ta = 1 - ta;
+    p2 = p1;
+    p1 = out;
+  }
+  HIPCHK(h, mhd::launch_diff_finish(c, c.U[s], p1, ta, tform, prev_t ? c.T[c.tcur] : nullptr));
+  return MHD_OK;
 }
 
 int mhd_launch_info(const mhd_ctx *h, int32_t *tile, int32_t *zseg, int32_t *blocks) {

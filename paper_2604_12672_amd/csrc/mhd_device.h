@@ -51,6 +51,16 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// (i, j, k) of a linear cell index q < nx ny nz (< 2^32: three state
+// copies of a larger grid would not fit in HBM), with 32-bit divisions
+__device__ __forceinline__ void cell_ijk(const Phys &ph, size_t q, int &i, int &j, int &k) {
+  const unsigned u = (unsigned)q, nx = (unsigned)ph.nx, ny = (unsigned)ph.ny;
+  const unsigned r = u / nx;
+  i = (int)(u - r * nx);
+  k = (int)(r / ny);
+  j = (int)(r - (unsigned)k * ny);
+}
+
 // ---------------------------------------------------------------------------
 // gas + radiation EOS (Sect. 2.2, eqs. prad, erad)
 // e_int(T) = C_g T + (a/rho) T^4, P = rho (R/mu) T + a T^4 / 3
@@ -139,6 +149,11 @@ struct PrimOut {
   int iters, fallback;
   int bad;       // 1 unphysical, 2 EOS failure
 };
+
+// forward EOS: e_int(rho, T) = C_g T + a T^4 / rho (eq. erad)
+__device__ __forceinline__ double specific_eint_rt(const Phys &ph, double rho, double T) {
+  return ph.cg * T + ph.arad * T * T * T * T * rcp<double>(rho);
+}
 
 // specific internal energy e_int = (E - rho v^2/2 - B_cc^2/2) / rho
 __device__ __forceinline__ double specific_eint(const double u[5], const double b[3]) {

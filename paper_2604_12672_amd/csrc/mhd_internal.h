@@ -56,6 +56,23 @@ struct StagePtrs {
   unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
 };
 
+// Thermal diffusion (RKL2): opacity law and conductivity prefactor
+struct DiffParams {
+  double pref;      // 4 a c / 3 (code units)
+  double alpha, beta;
+  double ikappa0;   // 1 / kappa0
+};
+
+// RKL2 work arrays (allocated on the first mhd_diffuse)
+struct DiffBufs {
+  double *e0 = nullptr;                 // e_int at the start
+  double *y[4] = {nullptr, nullptr, nullptr, nullptr};  // stage values (y[3]: T_0)
+  double *T[2] = {nullptr, nullptr};    // temperature of the last two stages
+  double *chi[2] = {nullptr, nullptr};  // chi = T^3 / (kappa rho) of the same
+  double *M0 = nullptr;                 // M[T_0] (over c_v0 in the T form)
+  double *cv0 = nullptr;                // c_v at the start
+};
+
 struct Ctx {
   mhd_grid_desc d;
   Phys ph;
@@ -80,6 +97,9 @@ struct Ctx {
   int *flags = nullptr;           // [1]
   unsigned long long *nstats = nullptr;  // [3]
   bool have_state = false;
+  DiffParams dparams{};
+  bool have_opacity = false;
+  DiffBufs diff;
   int zseg = 32;
   std::string err;
 };
@@ -102,6 +122,17 @@ size_t mlp_bytes();
 int stage_blocks_per_cu(const Ctx &c);
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
                             const double *Bz, double *Tg);
+hipError_t launch_diff_init(const Ctx &c, const double *U, const double *Bx, const double *By,
+                            const double *Bz, const double *Tg, int tform);
+hipError_t launch_diff_stage(const Ctx &c, const double *U, int ta, const double *y0,
+                             const double *y1, const double *y2, double *yn, int tform,
+                             int first, double mu, double nu, double mut, double gamt,
+                             double dt);
+hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, int tlast,
+                              int tform, double *Tstore);
+hipError_t launch_parabolic_dt(const Ctx &c, const double *U, const double *Bx,
+                               const double *By, const double *Bz, const double *Tg,
+                               double *dtp_dev);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0,
                             bool stats);

@@ -68,16 +68,6 @@ __device__ __forceinline__ int zface(const Phys &ph, int f) {
   return ph.reflect ? f : wrapi(f, ph.nz);
 }
 
-// (i, j, k) of a linear cell index q < nx ny nz (< 2^32: three state
-// copies of a larger grid would not fit in HBM), with 32-bit divisions
-__device__ __forceinline__ void cell_ijk(const Phys &ph, size_t q, int &i, int &j, int &k) {
-  const unsigned u = (unsigned)q, nx = (unsigned)ph.nx, ny = (unsigned)ph.ny;
-  const unsigned r = u / nx;
-  i = (int)(u - r * nx);
-  k = (int)(r / ny);
-  j = (int)(r - (unsigned)k * ny);
-}
-
 struct CellLoad {
   double u[5];
   double b[3];
@@ -146,30 +136,36 @@ __device__ __forceinline__ void recon_cell(int axis, const R *m, const R *c,
                                            bool pph) {
   const int vn = Q_VX + axis, v1 = Q_VX + (axis + 1) % 3, v2 = Q_VX + (axis + 2) % 3;
   const int b1 = Q_BX + (axis + 1) % 3, b2 = Q_BX + (axis + 2) % 3;
-  auto rec = [&](int f, R &l, R &h) {
-    if (pph) {
-      const R sixth = R(1.0 / 6.0);
-      l = (R(2) * m[f] + R(5) * c[f] - p[f]) * sixth;
-      h = (R(5) * c[f] - m[f] + R(2) * p[f]) * sixth;
+  auto rec_vl = [&](int f, R &l, R &h) {
+    const R s = R(0.5) * vanleer<R>(c[f] - m[f], p[f] - c[f]);
+    l = c[f] - s;
+    h = c[f] + s;
+  };
+  auto rec_pph = [&](int f, R &l, R &h) {
+    const R sixth = R(1.0 / 6.0);
+    l = (R(2) * m[f] + R(5) * c[f] - p[f]) * sixth;
+    h = (R(5) * c[f] - m[f] + R(2) * p[f]) * sixth;
+  };
+  // one uniform branch per cell and axis, not per field
+  auto all = [&](auto rec) {
+    rec(Q_RHO, lo.drho, hi.drho);
+    rec(vn, lo.vn, hi.vn);
+    rec(v1, lo.v1, hi.v1);
+    rec(v2, lo.v2, hi.v2);
+    rec(Q_P, lo.dp, hi.dp);
+    rec(b1, lo.b1, hi.b1);
+    rec(b2, lo.b2, hi.b2);
+    if (GR) {
+      rec(Q_GE, lo.dge, hi.dge);
+      rec(Q_GC, lo.dgc, hi.dgc);
     } else {
-      const R s = R(0.5) * vanleer<R>(c[f] - m[f], p[f] - c[f]);
-      l = c[f] - s;
-      h = c[f] + s;
+      lo.dge = hi.dge = lo.dgc = hi.dgc = R(0);
     }
   };
-  rec(Q_RHO, lo.drho, hi.drho);
-  rec(vn, lo.vn, hi.vn);
-  rec(v1, lo.v1, hi.v1);
-  rec(v2, lo.v2, hi.v2);
-  rec(Q_P, lo.dp, hi.dp);
-  rec(b1, lo.b1, hi.b1);
-  rec(b2, lo.b2, hi.b2);
-  if (GR) {
-    rec(Q_GE, lo.dge, hi.dge);
-    rec(Q_GC, lo.dgc, hi.dgc);
-  } else {
-    lo.dge = hi.dge = lo.dgc = hi.dgc = R(0);
-  }
+  if (pph)
+    all(rec_pph);
+  else
+    all(rec_vl);
 }
 
 template <typename R>

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libmhd.so")
 HOST, DEVICE = 0, 1
 PREC_FP64, PREC_SPLIT = 0, 1
 GUESS_PREV_T, GUESS_MLP = 0, 1
+DIFF_EINT, DIFF_TEMP = 0, 1
+C_LIGHT_CODE = 2.99792458e10 / 1e8  # speed of light in units of 1e8 cm/s
 RECON_VANLEER, RECON_PPH = 0, 1
 BC_PERIODIC, BC_REFLECT = 0, 1
 
@@ -56,7 +58,7 @@ class Diag(C.Structure):
 EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eos_mlp",
            "mhd_eos_solve", "mhd_set_state", "mhd_compute_dt", "mhd_step", "mhd_advance",
            "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
-           "mhd_launch_info"]
+           "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse"]
 
 _lib = None
 
@@ -92,6 +94,9 @@ def load():
     L.mhd_destroy.argtypes = [vp]
     L.mhd_launch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]
+    L.mhd_set_opacity.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.mhd_parabolic_dt.argtypes = [vp, C.POINTER(C.c_double)]
+    L.mhd_diffuse.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int if name != "mhd_last_error" else C.c_char_p
     _lib = L
@@ -302,6 +307,22 @@ class Grid:
                 "total": list(d.total), "bflux_x0": d.bflux_x0,
                 "newton_iters": d.newton_iters, "newton_max": d.newton_max,
                 "fallbacks": d.fallbacks, "error_flags": d.error_flags}
+
+    # -- thermal diffusion (RKL2) --------------------------------------------
+    def set_opacity(self, kappa0, alpha=0.0, beta=0.0, clight=C_LIGHT_CODE):
+        self._check(self._L.mhd_set_opacity(self._h, float(kappa0), float(alpha), float(beta),
+                                            float(clight)))
+
+    def parabolic_dt(self):
+        out = C.c_double(0.0)
+        self._check(self._L.mhd_parabolic_dt(self._h, C.byref(out)))
+        return out.value
+
+    def diffuse(self, dt, nsts=0, mode=DIFF_EINT):
+        """One RKL2 step; returns the number of stages used."""
+        used = C.c_int32(0)
+        self._check(self._L.mhd_diffuse(self._h, float(dt), int(nsts), int(mode), C.byref(used)))
+        return used.value
 
     def launch_info(self):
         t, z, b = C.c_int32(), C.c_int32(), C.c_int32()
