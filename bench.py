@@ -53,7 +53,14 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "9d0f79beb78dff51": {"fp64": (1473385.4, 1105572.9), "split": (1816550.3, 1220551.9)},
+    "995a36cc333eafa3": {"fp64": (1480055.9, 1107392.2), "split": (1784430.9, 1217114.1)},
+}
+
+
+# HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
+# dispatch, averaged over a super step) for the digest of its sources
+RKL2_TRAFFIC_KIB = {
+    "757db421d88dcea2": {"eint": (652679.8, 397803.5), "temp": (649163.6, 266731.5)},
 }
 
 
@@ -61,11 +68,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_digest():
-    """sha256 over the HIP sources of the library (first 16 hex digits)."""
+# the sources each measured kernel is compiled from
+STAGE_SOURCES = ("mhd_device.h", "mhd_internal.h", "mhd_kernels.hip")
+DIFFUSION_SOURCES = ("mhd_device.h", "mhd_diffusion.hip", "mhd_internal.h")
+
+
+def kernel_digest(names=STAGE_SOURCES):
+    """sha256 over the given HIP sources of the library (first 16 hex digits)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2604_12672_amd", "csrc")
-    for name in sorted(os.listdir(d)):
+    for name in sorted(names):
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -237,17 +249,28 @@ def split_error(mhd, n, steps):
             "reference": "FP64 GPU path (oracle-matched), same dt sequence"}
 
 
-# algorithmic bytes per cell of one RKL2 stage: reads y_(j-1), y_(j-2), y_0,
-# M_0, rho, T and chi of the previous stage (7 x 8 B), writes y_j, T, chi
-# (3 x 8 B); the temperature form also reads c_v0
-BYTES_RKL2_STAGE = {0: 80.0, 1: 88.0}
+# algorithmic bytes per cell of one RKL2 stage j >= 2.  Internal-energy form:
+# reads y_(j-1), y_(j-2), y_0, M_0, rho, and T and chi of the previous stage
+# (7 x 8 B), writes y_j, T, chi (3 x 8 B).  Temperature form: the stage value
+# is T, so it reads y_(j-1), y_(j-2), y_0, M_0, c_v0, rho, chi (7 x 8 B) and
+# writes y_j and chi (2 x 8 B).
+BYTES_RKL2_STAGE = {0: 80.0, 1: 72.0}
+
+
+def rkl2_traffic(mode_name):
+    t = RKL2_TRAFFIC_KIB.get(kernel_digest(DIFFUSION_SOURCES), {}).get(mode_name)
+    if t is None:
+        return None
+    return (t[0] * FETCH_FACTOR + t[1] * WRITE_FACTOR) * 1024.0
 
 
 def rkl2_bench(mhd, n):
     """One RKL2 super step of thermal diffusion on the gas+radiation box
     (n^3) with a Kramers-like opacity, dt = 100 parabolic limits (the
-    paper's stage count for that ratio); time per stage from HIP events
-    around the asynchronous call, in both forms."""
+    paper's stage count for that ratio), in both forms.  HIP events on the
+    library's stream around the asynchronous calls; the stage kernel's time
+    is the difference between super steps of 2s and s stages, divided by s,
+    so the set-up and finishing kernels cancel."""
     import torch
     from paper_2604_12672_amd import workloads as wl
     w = wl.config(3, n)
@@ -261,28 +284,36 @@ def rkl2_bench(mhd, n):
         s = g.diffuse(dt, 0, mode)  # warm-up, allocation, stage count
         g.sync()
         stream = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = 3
-        e0.record(stream)
-        for _ in range(reps):
-            g.diffuse(dt, s, mode)
-        e1.record(stream)
-        e1.synchronize()
-        g.sync()
-        ms = e0.elapsed_time(e1) / reps
+
+        def timed(nst, reps=3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                g.diffuse(dt, nst, mode)
+            e1.record(stream)
+            e1.synchronize()
+            g.sync()
+            return e0.elapsed_time(e1) / reps
+
+        ms = timed(s)
+        ms2 = timed(2 * s)
         g.close()
-        stage_ms = ms / s
-        achieved = BYTES_RKL2_STAGE[mode] * w.ncells / (stage_ms * 1e-3) / 1e9
+        stage_ms = (ms2 - ms) / s
+        bpc = BYTES_RKL2_STAGE[mode]
+        achieved = bpc * w.ncells / (stage_ms * 1e-3) / 1e9
+        tr = rkl2_traffic(name)
         res[name] = {"stages": s, "ms_per_super_step": round(ms, 4),
                      "ms_per_stage": round(stage_ms, 4),
                      "cell_stages_per_s": round(w.ncells / (stage_ms * 1e-3), 1),
                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                                  "kernel": "diff_stage_kernel",
-                                  "bytes_per_cell_stage": BYTES_RKL2_STAGE[mode]}}
-        log(f"bench: rkl2 {name}: {s} stages, {ms:.3f} ms per super step")
+                                  "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                  "traffic": None if tr is None else round(tr),
+                                  "kernel": "diff_stage_kernel<%s>" % ("true" if mode == mhd.DIFF_TEMP else "false"),
+                                  "bytes_per_cell_stage": bpc}}
+        log(f"bench: rkl2 {name}: {s} stages, {ms:.3f} ms per super step, "
+            f"{stage_ms:.4f} ms per stage")
     res["workload"] = (f"gas+radiation box {n}^3, kappa = 0.2 rho T^-3.5, one RKL2 super "
                        f"step of 100 parabolic limits")
     return res
@@ -340,8 +371,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="linear grid size of the headline box")
-    ap.add_argument("--only", choices=["fp64", "split"], default=None,
-                    help="run only this path of the headline box (profiling)")
+    ap.add_argument("--only", choices=["fp64", "split", "rkl2"], default=None,
+                    help="run only this path of the headline box, or only the RKL2 "
+                         "diffusion measurement (profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline box only (no gas+radiation, EOS, 512^3, turbulence)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -368,6 +400,10 @@ def main():
     mhd.load()
     torch.cuda.set_device(0)
     n = args.n
+    if args.only == "rkl2":
+        print(json.dumps({"rkl2_diffusion": rkl2_bench(mhd, n),
+                          "kernel_sources": kernel_digest(DIFFUSION_SOURCES)}), flush=True)
+        return
     log(f"bench: stratified box {n}^3 (kernel sources {kernel_digest()})")
     w = wl.stratified_box(n)
     res = {}

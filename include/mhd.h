@@ -215,9 +215,10 @@ int mhd_set_opacity(mhd_ctx *ctx, double kappa0, double alpha, double beta,
 int mhd_parabolic_dt(mhd_ctx *ctx, double *dtp_out);
 
 /* One RKL2 step of rho de_int/dt = div(K grad T) over dt (density, velocity
-   and field fixed; E changes by rho (e_new - e_old)), with nsts stages, or
-   when nsts <= 0 the paper's count max(1 + floor((sqrt(9 + 16 dt/dt_p) -
-   1)/2), 3) (that computes dt_p and synchronises).  mode MHD_DIFF_*.
+   and field fixed; E changes by rho (e_new - e_old)), with nsts stages
+   (2 <= nsts <= 100000, else MHD_ERR_ARG), or when nsts <= 0 the paper's
+   count max(1 + floor((sqrt(9 + 16 dt/dt_p) - 1)/2), 3) (that computes dt_p
+   and synchronises).  mode MHD_DIFF_*.
    *nsts_used (nullable) receives the stage count.  Reflecting z walls are
    insulating.  Asynchronous otherwise; errors latch as for mhd_step.  The
    work arrays (10 doubles per cell) are allocated on the first call. */

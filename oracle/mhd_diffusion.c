@@ -161,7 +161,8 @@ static int invert_all(const orc_cfg *c, const double *rho, const double *e, cons
 int orc_diffuse(const orc_cfg *c, const orc_opacity *op, double *U, const double *Bx,
                 const double *By, const double *Bz, double *T, double dt, int nsts,
                 int mode) {
-  if (c->eos != ORC_EOS_GASRAD || !(dt > 0.0) || nsts < 1) return ORC_ERR_ARG;
+  /* w1 = 4 / (s^2 + s - 2) needs s >= 2 */
+  if (c->eos != ORC_EOS_GASRAD || !(dt > 0.0) || nsts < 2) return ORC_ERR_ARG;
   const size_t n = (size_t)c->nx * c->ny * c->nz;
   double *rho = malloc(sizeof(double) * n), *e0 = malloc(sizeof(double) * n);
   double *y1 = malloc(sizeof(double) * n), *y2 = malloc(sizeof(double) * n);

@@ -319,7 +319,7 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.mlp);
   mhd::DiffBufs &d = c.diff;
   (void)hipFree(d.e0);
-  for (int i = 0; i < 4; ++i) (void)hipFree(d.y[i]);
+  for (int i = 0; i < 3; ++i) (void)hipFree(d.y[i]);
   for (int i = 0; i < 2; ++i) {
     (void)hipFree(d.T[i]);
     (void)hipFree(d.chi[i]);
@@ -691,12 +691,13 @@ int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts
   mhd::Ctx &c = h->c;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, MHD_ERR_ARG, "dt must be finite and > 0");
   if (mode != MHD_DIFF_EINT && mode != MHD_DIFF_TEMP) return fail(h, MHD_ERR_ARG, "bad mode");
+  if (nsts == 1) return fail(h, MHD_ERR_ARG, "RKL2 needs at least 2 stages");
   if (nsts > 100000) return fail(h, MHD_ERR_ARG, "nsts too large");
   mhd::DiffBufs &d = c.diff;
   if (!d.e0) {
     const size_t bytes = sizeof(double) * c.ncell;
     HIPCHK(h, hipMalloc(&d.e0, bytes));
-    for (int i = 0; i < 4; ++i) HIPCHK(h, hipMalloc(&d.y[i], bytes));
+    for (int i = 0; i < 3; ++i) HIPCHK(h, hipMalloc(&d.y[i], bytes));
     for (int i = 0; i < 2; ++i) {
       HIPCHK(h, hipMalloc(&d.T[i], bytes));
       HIPCHK(h, hipMalloc(&d.chi[i], bytes));
@@ -716,11 +717,13 @@ int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts
   const int tform = mode == MHD_DIFF_TEMP;
   const bool prev_t = c.d.eos_guess == MHD_GUESS_PREV_T;
   const double *Tg = prev_t ? c.T[c.tcur] : nullptr;
-  HIPCHK(h, mhd::launch_diff_init(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg, tform));
-  const double *y0 = tform ? d.y[3] : d.e0;
+  HIPCHK(h, mhd::launch_diff_init(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg));
+  // Y_0 is e_int, or T_0 in the temperature form, where the stage values are
+  // temperatures themselves and the T buffers only hold T_0
+  const double *y0 = tform ? d.T[0] : d.e0;
   const double *p1 = y0, *p2 = y0;
   const double w1 = 4.0 / ((double)nsts * nsts + nsts - 2.0);
-  int ta = 0;
+  int ta = 0;  // chi (and the e-form temperature) ping-pong between stages
   for (int j = 1; j <= nsts; ++j) {
     double mu = 0.0, nu = 0.0, mut, gamt = 0.0;
     if (j == 1) {
@@ -732,13 +735,16 @@ int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts
       gamt = -(1.0 - rkl2_b(j - 1)) * mut;
     }
     double *out = d.y[(j - 1) % 3];
-    HIPCHK(h, mhd::launch_diff_stage(c, c.U[s], ta, y0, p1, p2, out, tform, j == 1, mu, nu,
-                                     mut, gamt, dt));
+    const double *Ta = tform ? p1 : d.T[ta];
+    double *Tb = tform ? nullptr : d.T[1 - ta];
+    HIPCHK(h, mhd::launch_diff_stage(c, c.U[s], Ta, d.chi[ta], y0, p1, p2, out, Tb,
+                                     d.chi[1 - ta], tform, j == 1, mu, nu, mut, gamt, dt));
     ta = 1 - ta;
     p2 = p1;
     p1 = out;
   }
-  HIPCHK(h, mhd::launch_diff_finish(c, c.U[s], p1, ta, tform, prev_t ? c.T[c.tcur] : nullptr));
+  const double *Tlast = tform ? p1 : d.T[ta];
+  HIPCHK(h, mhd::launch_diff_finish(c, c.U[s], p1, Tlast, tform, prev_t ? c.T[c.tcur] : nullptr));
   return MHD_OK;
 }
 

@@ -51,6 +51,17 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// The logical block of physical block bid: XCD j (bid = j, j+8, ...) takes
+// the contiguous run [j q + min(j, r), ...) of the nblk logical blocks
+// (q = nblk / 8, r = nblk mod 8), a bijection onto [0, nblk), so blocks that
+// touch neighbouring data share one L2.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nblk) {
+  const int q8 = nblk / 8, r8 = nblk % 8;
+  const int xcd = bid % 8, slot = bid / 8;
+  return xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+}
+
 // (i, j, k) of a linear cell index q < nx ny nz (< 2^32: three state
 // copies of a larger grid would not fit in HBM), with 32-bit divisions
 __device__ __forceinline__ void cell_ijk(const Phys &ph, size_t q, int &i, int &j, int &k) {

@@ -62,18 +62,28 @@ __device__ __forceinline__ double diff_rhs(const Phys &ph, const DiffParams &dp,
   return div * rcp<double>(rho[q]);
 }
 
+// Cells [c0, c1) of this block.  Blocks take contiguous chunks of whole
+// 256-cell runs in XCD-contiguous logical order, so the rows and planes a
+// cell's neighbours live in are read by blocks that share one L2.
+__device__ __forceinline__ void block_cells(size_t n, size_t &c0, size_t &c1) {
+  const size_t span = (size_t)gridDim.x * blockDim.x;
+  const size_t per = (n + span - 1) / span * blockDim.x;
+  c0 = (size_t)xcd_logical_block(blockIdx.x, gridDim.x) * per;
+  c1 = c0 + per < n ? c0 + per : n;
+}
+
 // e_int, T (Newton from Tg, or the bracketed solve), c_v and chi of every
-// cell of the state; y0 = e_int or T (temperature form)
+// cell of the state
 __global__ __launch_bounds__(256) void diff_init_kernel(
     Phys ph, DiffParams dp, const double *__restrict__ U, const double *__restrict__ Bx,
     const double *__restrict__ By, const double *__restrict__ Bz,
-    const double *__restrict__ Tg, int tform, double *__restrict__ e0,
-    double *__restrict__ y0, double *__restrict__ T0, double *__restrict__ chi0,
-    double *__restrict__ cv0, int *flags) {
+    const double *__restrict__ Tg, double *__restrict__ e0, double *__restrict__ T0,
+    double *__restrict__ chi0, double *__restrict__ cv0, int *flags) {
   const size_t plane = (size_t)ph.nx * ph.ny;
   const size_t n = plane * ph.nz;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
+  size_t c0, c1;
+  block_cells(n, c0, c1);
+  for (size_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) {
     int i, j, k;
     cell_ijk(ph, q, i, j, k);
     const int ip = i + 1 == ph.nx ? 0 : i + 1;
@@ -98,45 +108,51 @@ __global__ __launch_bounds__(256) void diff_init_kernel(
     T0[q] = t;
     chi0[q] = chi_of(dp, rho, t);
     cv0[q] = ph.cg + 4.0 * ph.arad * t3 * rcp<double>(rho);
-    if (tform) y0[q] = t;
   }
 }
 
 // One RKL2 stage: yn = mu y1 + nu y2 + (1 - mu - nu) y0 + mut dt M[Ta] +
 // gamt dt M0 (first stage: yn = y0 + mut dt M[Ta], and M0 = M[Ta] is kept),
-// then the temperature and chi of yn.
+// then the temperature and chi of yn.  In the temperature form (TF) the
+// stage value is the temperature: Ta is y1 itself (y0 in the first stage),
+// M is divided by c_v0, and no separate temperature is read or written.
+template <bool TF>
 __global__ __launch_bounds__(256) void diff_stage_kernel(
     Phys ph, DiffParams dp, const double *__restrict__ U, const double *__restrict__ Ta,
     const double *__restrict__ chia, const double *__restrict__ y0,
     const double *__restrict__ y1, const double *__restrict__ y2, double *__restrict__ M0,
-    const double *__restrict__ cv0, int tform, int first, double mu, double nu, double mut,
+    const double *__restrict__ cv0, int first, double mu, double nu, double mut,
     double gamt, double dt, double *__restrict__ yn, double *__restrict__ Tb,
     double *__restrict__ chib, int *flags) {
   const size_t n = (size_t)ph.nx * ph.ny * ph.nz;
   const double *rho = U;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
+  const double *yp = TF ? Ta : y1;
+  size_t c0, c1;
+  block_cells(n, c0, c1);
+  for (size_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) {
     int i, j, k;
     cell_ijk(ph, q, i, j, k);
+    const double r = rho[q];
     double M = diff_rhs(ph, dp, rho, Ta, chia, q, i, j, k);
-    if (tform) M *= rcp<double>(cv0[q]);
+    if (TF) M *= rcp<double>(cv0[q]);
     double v;
     if (first) {
       M0[q] = M;
       v = y0[q] + mut * dt * M;
     } else {
-      v = mu * y1[q] + nu * y2[q] + (1.0 - mu - nu) * y0[q] + mut * dt * M + gamt * dt * M0[q];
+      v = mu * yp[q] + nu * y2[q] + (1.0 - mu - nu) * y0[q] + mut * dt * M + gamt * dt * M0[q];
     }
     yn[q] = v;
     double t = v;
-    if (!tform) {
+    if (!TF) {
       int it, fb;
-      const double r = rho[q];
       if (!(v > 0.0) || eos_temperature(ph, r, v, Ta[q], ph.newton_maxit, t, it, fb))
         atomicOr(flags, 2);
+      Tb[q] = t;
+    } else if (!(v > 0.0)) {
+      atomicOr(flags, 2);
     }
-    Tb[q] = t;
-    chib[q] = chi_of(dp, rho[q], t);
+    chib[q] = chi_of(dp, r, t);
   }
 }
 
@@ -146,11 +162,11 @@ __global__ __launch_bounds__(256) void diff_finish_kernel(
     const double *__restrict__ ylast, const double *__restrict__ Tlast, int tform,
     double *__restrict__ Tstore) {
   const size_t n = (size_t)ph.nx * ph.ny * ph.nz;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
+  size_t c0, c1;
+  block_cells(n, c0, c1);
+  for (size_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) {
     const double rho = U[q];
-    double enew = ylast[q];
-    if (tform) enew = specific_eint_rt(ph, rho, Tlast[q]);
+    const double enew = tform ? specific_eint_rt(ph, rho, Tlast[q]) : ylast[q];
     U[4 * n + q] += rho * (enew - e0[q]);
     if (Tstore) Tstore[q] = Tlast[q];
   }
@@ -229,30 +245,34 @@ static int grid_blocks(const Ctx &c) {
 }
 
 hipError_t launch_diff_init(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, const double *Tg, int tform) {
+                            const double *Bz, const double *Tg) {
   const DiffBufs &d = c.diff;
   hipLaunchKernelGGL(diff_init_kernel, dim3(grid_blocks(c)), dim3(256), 0, c.stream, c.ph,
-                     c.dparams, U, Bx, By, Bz, Tg, tform, d.e0, d.y[3], d.T[0], d.chi[0],
-                     d.cv0, c.flags);
+                     c.dparams, U, Bx, By, Bz, Tg, d.e0, d.T[0], d.chi[0], d.cv0, c.flags);
   return hipGetLastError();
 }
 
-hipError_t launch_diff_stage(const Ctx &c, const double *U, int ta, const double *y0,
-                             const double *y1, const double *y2, double *yn, int tform,
-                             int first, double mu, double nu, double mut, double gamt,
-                             double dt) {
+hipError_t launch_diff_stage(const Ctx &c, const double *U, const double *Ta, const double *chia,
+                             const double *y0, const double *y1, const double *y2, double *yn,
+                             double *Tb, double *chib, int tform, int first, double mu,
+                             double nu, double mut, double gamt, double dt) {
   const DiffBufs &d = c.diff;
-  hipLaunchKernelGGL(diff_stage_kernel, dim3(grid_blocks(c)), dim3(256), 0, c.stream, c.ph,
-                     c.dparams, U, d.T[ta], d.chi[ta], y0, y1, y2, d.M0, d.cv0, tform, first,
-                     mu, nu, mut, gamt, dt, yn, d.T[1 - ta], d.chi[1 - ta], c.flags);
+  if (tform)
+    hipLaunchKernelGGL(diff_stage_kernel<true>, dim3(grid_blocks(c)), dim3(256), 0, c.stream,
+                       c.ph, c.dparams, U, Ta, chia, y0, y1, y2, d.M0, d.cv0, first, mu, nu,
+                       mut, gamt, dt, yn, Tb, chib, c.flags);
+  else
+    hipLaunchKernelGGL(diff_stage_kernel<false>, dim3(grid_blocks(c)), dim3(256), 0, c.stream,
+                       c.ph, c.dparams, U, Ta, chia, y0, y1, y2, d.M0, d.cv0, first, mu, nu,
+                       mut, gamt, dt, yn, Tb, chib, c.flags);
   return hipGetLastError();
 }
 
-hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, int tlast,
+hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, const double *Tlast,
                               int tform, double *Tstore) {
   const DiffBufs &d = c.diff;
   hipLaunchKernelGGL(diff_finish_kernel, dim3(grid_blocks(c)), dim3(256), 0, c.stream, c.ph, U,
-                     d.e0, ylast, d.T[tlast], tform, Tstore);
+                     d.e0, ylast, Tlast, tform, Tstore);
   return hipGetLastError();
 }
 

@@ -66,8 +66,8 @@ struct DiffParams {
 // RKL2 work arrays (allocated on the first mhd_diffuse)
 struct DiffBufs {
   double *e0 = nullptr;                 // e_int at the start
-  double *y[4] = {nullptr, nullptr, nullptr, nullptr};  // stage values (y[3]: T_0)
-  double *T[2] = {nullptr, nullptr};    // temperature of the last two stages
+  double *y[3] = {nullptr, nullptr, nullptr};  // stage values Y_j, rotated
+  double *T[2] = {nullptr, nullptr};    // temperature of the last two stages (T[0]: T_0)
   double *chi[2] = {nullptr, nullptr};  // chi = T^3 / (kappa rho) of the same
   double *M0 = nullptr;                 // M[T_0] (over c_v0 in the T form)
   double *cv0 = nullptr;                // c_v at the start
@@ -123,12 +123,12 @@ int stage_blocks_per_cu(const Ctx &c);
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
                             const double *Bz, double *Tg);
 hipError_t launch_diff_init(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, const double *Tg, int tform);
-hipError_t launch_diff_stage(const Ctx &c, const double *U, int ta, const double *y0,
-                             const double *y1, const double *y2, double *yn, int tform,
-                             int first, double mu, double nu, double mut, double gamt,
-                             double dt);
-hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, int tlast,
+                            const double *Bz, const double *Tg);
+hipError_t launch_diff_stage(const Ctx &c, const double *U, const double *Ta, const double *chia,
+                             const double *y0, const double *y1, const double *y2, double *yn,
+                             double *Tb, double *chib, int tform, int first, double mu,
+                             double nu, double mut, double gamt, double dt);
+hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, const double *Tlast,
                               int tform, double *Tstore);
 hipError_t launch_parabolic_dt(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz, const double *Tg,

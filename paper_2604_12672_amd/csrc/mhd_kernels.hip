@@ -260,18 +260,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   const int tid = threadIdx.x;
   const int tx = tid % TT, ty = tid / TT;
   const int ci = tx - 1, cj = ty - 1;
-  // Blocks are dealt round-robin to the 8 XCDs (separate L2 caches); remap
-  // so that each XCD works through a contiguous run of tiles (x fastest,
-  // then y, then z segment) and neighbouring tiles share its L2.
+  // each XCD works through a contiguous run of tiles (x fastest, then y,
+  // then z segment), so neighbouring tiles share its L2
   const int ntx = (ph.nx + TB - 1) / TB, nty = (ph.ny + TB - 1) / TB;
-  const int nblk = gridDim.x;
-  const int bid = blockIdx.x;
-  // XCD j receives the blocks bid = j, j+8, ...: ceil((nblk - j)/8) of them;
-  // they take the logical blocks [j q + min(j, r), ...) (q = nblk/8,
-  // r = nblk mod 8), a bijection onto [0, nblk)
-  const int q8 = nblk / 8, r8 = nblk % 8;
-  const int xcd = bid % 8, slot = bid / 8;
-  const int lb = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int btx = lb % ntx, bty = (lb / ntx) % nty, bsz = lb / (ntx * nty);
   const int X0 = btx * TB, Y0 = bty * TB;
   const int z0 = bsz * zseg;

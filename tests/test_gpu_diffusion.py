@@ -144,6 +144,8 @@ def test_diffusion_error_paths(mhd):
         g.diffuse(-1.0, 5)
     with pytest.raises(mhd.MHDError):
         g.diffuse(1.0, 5, mode=7)
+    with pytest.raises(mhd.MHDError):
+        g.diffuse(1.0, 1)  # w1 = 4 / (s^2 + s - 2) needs two stages
     g.close()
     gi = mhd.Grid(wl.base_params(4, 4, 4))
     with pytest.raises(mhd.MHDError):

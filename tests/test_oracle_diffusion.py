@@ -110,6 +110,15 @@ def test_internal_energy_is_conserved(mode, bcz):
     assert st["T"].max() < T.max() and st["T"].min() > T.min()
 
 
+def test_single_stage_is_rejected():
+    # w1 = 4 / (s^2 + s - 2) is undefined for s = 1
+    p = wl.gasrad_params(4, 4, 4)
+    rng = np.random.default_rng(14)
+    st = _state(p, np.ones((4, 4, 4)), 10.0 ** rng.uniform(6, 7, size=(4, 4, 4)))
+    with pytest.raises(orc.OracleError):
+        orc.Oracle(p).diffuse(st, 1e-3, 1, orc.opacity(0.2, alpha=1.0, beta=-3.5))
+
+
 def test_uniform_temperature_is_steady():
     p = wl.gasrad_params(6, 5, 4)
     shp = (4, 5, 6)
