@@ -396,6 +396,32 @@ int orc_riemann(const orc_cfg *c, const double *WL, const double *WR,
   return ORC_OK;
 }
 
+/* HLL (Harten, Lax & van Leer 1983), the two-wave solver of flattened
+   cells (Sect. 2.7): one intermediate state between the fastest waves,
+   F = (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L), upwind
+   outside the fan; the wave speeds are those of orc_riemann. */
+int orc_hll(const orc_cfg *c, const double *WL, const double *WR, double bn,
+            double *flux) {
+  (void)c;
+  side_t L, R;
+  side_setup(WL, bn, &L);
+  side_setup(WR, bn, &R);
+  double cmax = fmax(L.cf, R.cf);
+  double SL = fmin(L.vn, R.vn) - cmax;
+  double SR = fmax(L.vn, R.vn) + cmax;
+  if (0.0 <= SL) {
+    memcpy(flux, L.F, sizeof(L.F));
+    return ORC_OK;
+  }
+  if (SR < 0.0) {
+    memcpy(flux, R.F, sizeof(R.F));
+    return ORC_OK;
+  }
+  for (int q = 0; q < NFLUX; ++q)
+    flux[q] = (SR * L.F[q] - SL * R.F[q] + SL * SR * (R.U[q] - L.U[q])) / (SR - SL);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Grid helpers                                                         */
 /* ------------------------------------------------------------------ */
@@ -456,6 +482,80 @@ static void cell_field(const orc_cfg *c, const grid_t *g, const double *Bx,
   b[0] = 0.5 * (Bx[cidx(g, i, j, k)] + Bx[cidx(g, ip, j, k)]);
   b[1] = 0.5 * (By[cidx(g, i, j, k)] + By[cidx(g, i, jp, k)]);
   b[2] = 0.5 * (Bz[cidx(g, i, j, k)] + Bz[cidx(g, i, j, kp)]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Shock flattening (Sect. 2.7)                                         */
+/* ------------------------------------------------------------------ */
+
+/* Flags from the thermal pressure P [nz][ny][nx] of every cell.
+   Detector: (|P_{i+1} - P_{i-1}| + |P_{j+1} - P_{j-1}| + |P_{k+1} - P_{k-1}|)
+   / (eps_SF P) > 1, the neighbours taken periodically in x and y and in a
+   periodic z, and as mirror images at a reflecting wall (P is even, so the
+   image of cell 0 below the wall is cell 0 itself).  Every cell within the
+   5x5x5 cube (two cells per axis) of a detected cell is flagged; across a
+   wall the cube is cut off (a mirror image only repeats cells inside it). */
+static void shock_flags_from_p(const orc_cfg *c, const grid_t *g, const double *P,
+                               unsigned char *flags) {
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const size_t n = (size_t)nx * ny * nz;
+  unsigned char *det = (unsigned char *)malloc(n);
+#pragma omp parallel for collapse(3) schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        int mir;
+        const int km = zsrc(c, k - 1, &mir), kp = zsrc(c, k + 1, &mir);
+        const double sum =
+            fabs(P[cidx(g, wrap(i + 1, nx), j, k)] - P[cidx(g, wrap(i - 1, nx), j, k)]) +
+            fabs(P[cidx(g, i, wrap(j + 1, ny), k)] - P[cidx(g, i, wrap(j - 1, ny), k)]) +
+            fabs(P[cidx(g, i, j, kp)] - P[cidx(g, i, j, km)]);
+        det[cidx(g, i, j, k)] = sum / (c->eps_sf * P[cidx(g, i, j, k)]) > 1.0;
+      }
+#pragma omp parallel for collapse(3) schedule(static)
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        unsigned char f = 0;
+        for (int dk = -2; dk <= 2; ++dk) {
+          int kk = k + dk;
+          if (c->bcz == ORC_BC_REFLECT) {
+            if (kk < 0 || kk >= nz) continue;
+          } else {
+            kk = wrap(kk, nz);
+          }
+          for (int dj = -2; dj <= 2; ++dj)
+            for (int di = -2; di <= 2; ++di)
+              f |= det[cidx(g, wrap(i + di, nx), wrap(j + dj, ny), kk)];
+        }
+        flags[cidx(g, i, j, k)] = f;
+      }
+  free(det);
+}
+
+int orc_shock_flags(const orc_cfg *c, const double *U, const double *Bx,
+                    const double *By, const double *Bz, const double *Tguess,
+                    unsigned char *flags) {
+  grid_t g;
+  grid_init(c, &g);
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  double *P = (double *)malloc(sizeof(double) * n);
+  int err = ORC_OK;
+#pragma omp parallel for collapse(3) schedule(static) reduction(min : err)
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        const size_t q = cidx(&g, i, j, k);
+        double u[5], b[3], w[NWF], t = 0.0;
+        for (int f = 0; f < 5; ++f) u[f] = U[f * n + q];
+        cell_field(c, &g, Bx, By, Bz, i, j, k, b);
+        const int rc = cons2prim(c, u, b, Tguess ? Tguess[q] : 0.0, &t, w);
+        if (rc < err) err = rc;
+        P[q] = w[W_P];
+      }
+  if (!err) shock_flags_from_p(c, &g, P, flags);
+  free(P);
+  return err;
 }
 
 int orc_primitives(const orc_cfg *c, const double *U, const double *Bx,
@@ -525,6 +625,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
   /* steps 1-2: primitives and their deviation from the background */
   double *dW = (double *)malloc(sizeof(double) * NWF * G);
   double *Tnew = (double *)malloc(sizeof(double) * n);
+  double *Pc = (double *)malloc(sizeof(double) * n); /* thermal P per cell */
 #pragma omp parallel for collapse(3) schedule(static) reduction(min : err)
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
@@ -536,6 +637,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
         int rc = cons2prim(c, u, b, Tguess ? Tguess[q] : 0.0, &t, w);
         if (rc < err) err = rc;
         Tnew[q] = t;
+        Pc[q] = w[W_P];
         /* Delta W = W - W_hat (Sect. 2.8); the background has zero velocity
            and field, so only rho, P, gamma_e, gamma_c change */
         w[W_RHO] -= bg_cell(c, 0, k);
@@ -548,10 +650,30 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
   if (err) {
     free(dW);
     free(Tnew);
+    free(Pc);
     return err;
   }
   if (Tout) memcpy(Tout, Tnew, sizeof(double) * n);
   free(Tnew);
+
+  /* shock flattening (Sect. 2.7): flags of the stage's input state on the
+     padded grid, ghosts filled like the primitives below (a mirror image
+     carries the flag of its source cell) */
+  unsigned char *flg = NULL;
+  if (c->flatten) {
+    unsigned char *fi = (unsigned char *)malloc(n);
+    shock_flags_from_p(c, &g, Pc, fi);
+    flg = (unsigned char *)calloc(G, 1);
+    for (int k = -NG; k < nz + NG; ++k) {
+      int mir;
+      const int ks = zsrc(c, k, &mir);
+      for (int j = -NG; j < ny + NG; ++j)
+        for (int i = -NG; i < nx + NG; ++i)
+          flg[gidx(&g, i, j, k)] = fi[cidx(&g, wrap(i, nx), wrap(j, ny), ks)];
+    }
+    free(fi);
+  }
+  free(Pc);
 
   /* step 3: ghost cells -- x and y periodic; z periodic or mirrored */
   for (int k = 0; k < nz; ++k)
@@ -625,17 +747,25 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
           const int fl[9] = {W_RHO,        vel_of[d][0], vel_of[d][1],
                              vel_of[d][2], W_P,          fld_of[d][1],
                              fld_of[d][2], W_GE,         W_GC};
+          /* flattened cells: van Leer reconstruction, and the HLL solver
+             on every face that touches one (Sect. 2.7) */
+          const int fL = flg ? flg[pL] : 0, fR = flg ? flg[pR] : 0;
+          const int pphL = c->recon == ORC_RECON_PPH && !fL;
+          const int pphR = c->recon == ORC_RECON_PPH && !fR;
           double WL[9], WR[9];
           for (int m = 0; m < 9; ++m) {
             const double *a = dW + (size_t)fl[m] * G;
-            if (c->recon == ORC_RECON_PPH) {
-              double unused;
+            double unused;
+            if (pphL) {
               orc_pph(a[pL - st], a[pL], a[pR], &unused, &WL[m]);
-              orc_pph(a[pL], a[pR], a[pR + st], &WR[m], &unused);
             } else {
               double sL = orc_vanleer(a[pL] - a[pL - st], a[pR] - a[pL]);
-              double sR = orc_vanleer(a[pR] - a[pL], a[pR + st] - a[pR]);
               WL[m] = a[pL] + 0.5 * sL; /* Delta W_{i-1/2, L} */
+            }
+            if (pphR) {
+              orc_pph(a[pL], a[pR], a[pR + st], &WR[m], &unused);
+            } else {
+              double sR = orc_vanleer(a[pR] - a[pL], a[pR + st] - a[pR]);
               WR[m] = a[pR] - 0.5 * sR; /* Delta W_{i-1/2, R} */
             }
           }
@@ -678,6 +808,8 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
           if (!(WL[0] > 0.0 && WR[0] > 0.0 && WL[4] > 0.0 && WR[4] > 0.0)) {
             ferr = ORC_ERR_UNPHYSICAL;
             for (int q = 0; q < NFLUX; ++q) fx[q] = 0.0;
+          } else if (fL || fR) {
+            orc_hll(c, WL, WR, bn, fx);
           } else {
             orc_riemann(c, WL, WR, bn, fx);
           }
@@ -689,6 +821,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
   }
   free(Fh_c);
   free(Fh_f);
+  free(flg);
   if (err) goto done;
 
   {

@@ -59,6 +59,8 @@ typedef struct {
   double mach_cut;       /* Mach threshold of the low-dissipation factor   */
   int xi_mode;           /* ORC_XI_*                                        */
   int recon;             /* ORC_RECON_*                                     */
+  int flatten;           /* 1: shock flattening (Sect. 2.7), 0: off         */
+  double eps_sf;         /* threshold epsilon_SF of the shock detector      */
   const double *bg_cc;   /* [4][nz]  background rho, P, gamma_e, gamma_c at
                             cell centres, or NULL for a zero background     */
   const double *bg_fz;   /* [4][nzf] the same at z faces (NULL with bg_cc)  */
@@ -89,6 +91,19 @@ void orc_pph(double wm, double wc, double wp, double *lo, double *hi);
    flux = {mass, mom_n, mom_t1, mom_t2, energy, B_t1, B_t2}. */
 int orc_riemann(const orc_cfg *c, const double *WL, const double *WR,
                 double bn, double *flux);
+
+/* HLL two-wave flux (Harten, Lax & van Leer 1983; the solver of flattened
+   cells, Sect. 2.7) with the same wave-speed estimates as orc_riemann;
+   same arguments and layout. */
+int orc_hll(const orc_cfg *c, const double *WL, const double *WR, double bn,
+            double *flux);
+
+/* Shock-flattening flags of every cell (Sect. 2.7): the detector on the
+   thermal pressure of the state, dilated over the 5x5x5 neighbourhood.
+   flags [nz][ny][nx] = 1 (flattened) or 0.  Tguess as for orc_residual. */
+int orc_shock_flags(const orc_cfg *c, const double *U, const double *Bx,
+                    const double *By, const double *Bz, const double *Tguess,
+                    unsigned char *flags);
 
 /* Spatial residual R(U) of eq. spatres for cells and faces; dU/dt = -RU,
    dB/dt = -RB.  Tguess/Tout: EOS guess and result (gas+radiation only;

@@ -33,6 +33,7 @@ class _Cfg(C.Structure):
         ("rk_order", C.c_int), ("newton_tol", C.c_double),
         ("newton_maxit", C.c_int), ("mach_cut", C.c_double),
         ("xi_mode", C.c_int), ("recon", C.c_int),
+        ("flatten", C.c_int), ("eps_sf", C.c_double),
         ("bg_cc", _DP), ("bg_fz", _DP), ("heat", _DP), ("force", _DP),
     ]
 
@@ -62,6 +63,8 @@ def lib():
         L.orc_divb.restype = None
         L.orc_primitives.argtypes = [C.POINTER(_Cfg)] + [_DP] * 7
         L.orc_riemann.argtypes = [C.POINTER(_Cfg), _DP, _DP, C.c_double, _DP]
+        L.orc_hll.argtypes = [C.POINTER(_Cfg), _DP, _DP, C.c_double, _DP]
+        L.orc_shock_flags.argtypes = [C.POINTER(_Cfg)] + [_DP] * 5 + [C.POINTER(C.c_ubyte)]
         L.orc_eos_invert.argtypes = [C.POINTER(_Cfg), C.c_double, C.c_double,
                                      C.c_double, _DP, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]
@@ -102,7 +105,7 @@ def _check(rc, what):
 DEFAULTS = dict(
     bcz=BC_PERIODIC, eos=EOS_IDEAL, gamma=5.0 / 3.0, mu=0.6, rgas=0.0, arad=0.0,
     gz=0.0, rk_order=2, newton_tol=1e-11, newton_maxit=50, mach_cut=0.6,
-    xi_mode=XI_LINEAR, recon=RECON_VANLEER,
+    xi_mode=XI_LINEAR, recon=RECON_VANLEER, flatten=0, eps_sf=0.2,
 )
 
 
@@ -128,7 +131,7 @@ class Oracle:
             int(p["bcz"]), int(p["eos"]), float(p["gamma"]), float(p["mu"]),
             float(p["rgas"]), float(p["arad"]), float(p["gz"]), int(p["rk_order"]),
             float(p["newton_tol"]), int(p["newton_maxit"]), float(p["mach_cut"]),
-            int(p["xi_mode"]), int(p["recon"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
+            int(p["xi_mode"]), int(p["recon"]), int(p["flatten"]), float(p["eps_sf"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
         )
 
     # -- state helpers -------------------------------------------------
@@ -212,6 +215,23 @@ class Oracle:
         _check(lib().orc_riemann(C.byref(self.cfg), _ptr(WL), _ptr(WR), float(bn), _ptr(F)),
                "orc_riemann")
         return F
+
+    def hll(self, WL, WR, bn):
+        WL = np.ascontiguousarray(WL, dtype=np.float64)
+        WR = np.ascontiguousarray(WR, dtype=np.float64)
+        F = np.empty(7)
+        _check(lib().orc_hll(C.byref(self.cfg), _ptr(WL), _ptr(WR), float(bn), _ptr(F)),
+               "orc_hll")
+        return F
+
+    def shock_flags(self, st: dict) -> np.ndarray:
+        """Shock-flattening flags (0/1, uint8) of every cell of the state."""
+        U, Bx, By, Bz, T = self._state(st)
+        out = np.zeros(self.shape, dtype=np.uint8)
+        _check(lib().orc_shock_flags(C.byref(self.cfg), _ptr(U), _ptr(Bx), _ptr(By), _ptr(Bz),
+                                     _ptr(T), out.ctypes.data_as(C.POINTER(C.c_ubyte))),
+               "orc_shock_flags")
+        return out
 
     def eos_invert(self, rho, eint, tguess):
         T = C.c_double(0.0)
