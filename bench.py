@@ -121,9 +121,11 @@ def gpu_run(mhd, w, precision, steps, warmup, mlp=None):
     g.sync()
     stage_ms = e0.elapsed_time(e1) / (float(w.params.get("rk_order", 2)) * nrep)
     info = g.launch_info()
+    flagged = float(g.shock_flags().mean()) if w.params.get("flatten") else None
     g.close()
     return {"wall": wall, "stage_ms": stage_ms, "diag": diag, "info": info,
-            "ms": wall / steps * 1e3, "value": w.ncells * steps / wall, "learned": mlp is not None}
+            "ms": wall / steps * 1e3, "value": w.ncells * steps / wall, "learned": mlp is not None,
+            "flagged": flagged}
 
 
 def stage_bytes(w, learned):
@@ -365,15 +367,40 @@ def summary(w, r, path):
             "roofline": roofline(w, r["stage_ms"], path, r["learned"]), "divb_max": r["diag"]["divb_max"]}
 
 
+def turbulence_bench(mhd, model, args):
+    """Config 4 (forced MHD turbulence, learned guess, split precision),
+    without and with shock flattening."""
+    from paper_2604_12672_amd import workloads as wl
+    log(f"bench: turbulence box {args.turb_n}^3")
+    wt = wl.turbulence_box(args.turb_n)
+    tr = gpu_run(mhd, wt, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
+    t = dict(summary(wt, tr, "turbulence_split_learned"), **newton_stats(wt, tr["diag"]))
+    t["workload"] = (f"forced MHD turbulence {args.turb_n}^3, rms Mach 3, beta 1, "
+                     f"gas+radiation, learned guess, split precision")
+    log(f"bench: turbulence {tr['ms']:.3f} ms/step, divB {tr['diag']['divb_max']:.2e}")
+    # the same run with shock flattening: flags of every stage input
+    # (pressure, detector, 5x5x5 dilation), HLL and van Leer where flagged
+    wt.params = dict(wt.params, flatten=1)
+    tf = gpu_run(mhd, wt, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
+    tflat = {
+        "value": round(tf["value"], 1), "ms_per_step": round(tf["ms"], 4),
+        "overhead_vs_unflattened": round(tf["ms"] / tr["ms"] - 1.0, 4),
+        "flagged_fraction_at_end": round(tf["flagged"], 5),
+        "divb_max": tf["diag"]["divb_max"],
+        "workload": t["workload"] + ", shock flattening (eps_SF 0.2)"}
+    log(f"bench: turbulence flattened {tf['ms']:.3f} ms/step, flagged {tf['flagged']:.4f}")
+    return t, tflat
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="linear grid size of the headline box")
-    ap.add_argument("--only", choices=["fp64", "split", "rkl2"], default=None,
+    ap.add_argument("--only", choices=["fp64", "split", "rkl2", "turbulence"], default=None,
                     help="run only this path of the headline box, or only the RKL2 "
-                         "diffusion measurement (profiling)")
+                         "diffusion or the turbulence measurement (profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline box only (no gas+radiation, EOS, 512^3, turbulence)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -400,6 +427,10 @@ def main():
     mhd.load()
     torch.cuda.set_device(0)
     n = args.n
+    if args.only == "turbulence":
+        t, tf = turbulence_bench(mhd, eos_mlp.MLPGuess.load(), args)
+        print(json.dumps({"turbulence": t, "turbulence_flattened": tf}), flush=True)
+        return
     if args.only == "rkl2":
         print(json.dumps({"rkl2_diffusion": rkl2_bench(mhd, n),
                           "kernel_sources": kernel_digest(DIFFUSION_SOURCES)}), flush=True)
@@ -498,15 +529,7 @@ def main():
             f"{args.split_steps} steps")
         out["split_error"] = split_error(mhd, args.split_n, args.split_steps)
         log(f"bench: split error {out['split_error']['rel_l2_vs_fp64']}")
-        log(f"bench: turbulence box {args.turb_n}^3")
-        wt = wl.turbulence_box(args.turb_n)
-        tr = gpu_run(mhd, wt, mhd.PREC_SPLIT, args.steps, args.warmup, mlp=model)
-        t = dict(summary(wt, tr, "turbulence_split_learned"), **newton_stats(wt, tr["diag"]))
-        t["workload"] = (f"forced MHD turbulence {args.turb_n}^3, rms Mach 3, beta 1, "
-                         f"gas+radiation, learned guess, split precision")
-        out["turbulence"] = t
-        log(f"bench: turbulence {tr['ms']:.3f} ms/step, divB {tr['diag']['divb_max']:.2e}")
-        del wt
+        out["turbulence"], out["turbulence_flattened"] = turbulence_bench(mhd, model, args)
     if not args.no_extras and not args.only:
         out["rkl2_diffusion"] = rkl2_bench(mhd, args.n)
     if not args.no_cpu_baseline:

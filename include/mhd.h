@@ -104,6 +104,8 @@ typedef struct {
   double mach_cut;        /* Mach threshold of the LHLLD factor (paper: 0.6)   */
   int32_t xi_mode;        /* MHD_XI_*                                          */
   int32_t recon;          /* MHD_RECON_*                                       */
+  int32_t flatten;        /* 1: shock flattening (Sect. 2.7), 0: off           */
+  double eps_sf;          /* detector threshold epsilon_SF (paper: 0.2), > 0   */
 } mhd_grid_desc;
 
 typedef struct {
@@ -194,6 +196,13 @@ int mhd_advance(mhd_ctx *ctx, double cfl, int32_t nsteps);
    the guess kept for the next step is not changed. */
 int mhd_get_state(mhd_ctx *ctx, double *U, double *Bx, double *By, double *Bz,
                   double *T, int32_t where);
+
+/* Shock-flattening flags (Sect. 2.7) of the current state, one byte per
+   cell [nz][ny][nx] (1 = flattened: van Leer reconstruction and HLL on its
+   faces), as the next stage would compute them: the detector on the thermal
+   pressure, dilated over the 5x5x5 neighbourhood.  Contexts created with
+   flatten = 1 only (else MHD_ERR_STATE).  Synchronises. */
+int mhd_shock_flags(mhd_ctx *ctx, uint8_t *flags, int32_t where);
 
 /* Wait for queued work; returns latched device errors. */
 int mhd_sync(mhd_ctx *ctx);

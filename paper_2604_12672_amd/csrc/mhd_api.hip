@@ -109,6 +109,14 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "recon must be MHD_RECON_VANLEER or MHD_RECON_PPH";
     return MHD_ERR_ARG;
   }
+  if (d->flatten != 0 && d->flatten != 1) {
+    msg = "flatten must be 0 or 1";
+    return MHD_ERR_ARG;
+  }
+  if (d->flatten && !(d->eps_sf > 0.0 && std::isfinite(d->eps_sf))) {
+    msg = "eps_sf must be finite and > 0";
+    return MHD_ERR_ARG;
+  }
   if (d->eos_guess != MHD_GUESS_PREV_T && d->eos_guess != MHD_GUESS_MLP) {
     msg = "unknown eos_guess";
     return MHD_ERR_ARG;
@@ -287,6 +295,13 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   if ((e = hipMalloc(&c.flags, sizeof(int))) != hipSuccess) return cleanup(e, "hipMalloc flags");
   if ((e = hipMalloc(&c.nstats, sizeof(unsigned long long) * 3)) != hipSuccess)
     return cleanup(e, "hipMalloc stats");
+  if (desc->flatten) {
+    if ((e = hipMalloc(&c.shock_p, sizeof(double) * c.ncell)) != hipSuccess)
+      return cleanup(e, "hipMalloc shock pressure");
+    for (int i = 0; i < 2; ++i)
+      if ((e = hipMalloc(&c.shock_f[i], c.ncell)) != hipSuccess)
+        return cleanup(e, "hipMalloc shock flags");
+  }
   if ((e = hipMemsetAsync(c.flags, 0, sizeof(int), c.stream)) != hipSuccess)
     return cleanup(e, "hipMemset flags");
   if ((e = hipMemsetAsync(c.nstats, 0, sizeof(unsigned long long) * 3, c.stream)) != hipSuccess)
@@ -317,6 +332,9 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.flags);
   (void)hipFree(c.nstats);
   (void)hipFree(c.mlp);
+  (void)hipFree(c.shock_p);
+  (void)hipFree(c.shock_f[0]);
+  (void)hipFree(c.shock_f[1]);
   mhd::DiffBufs &d = c.diff;
   (void)hipFree(d.e0);
   for (int i = 0; i < 3; ++i) (void)hipFree(d.y[i]);
@@ -437,6 +455,11 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.Tin = prev_t ? c.T[c.tcur] : (learned ? c.T[0] : nullptr);
     p.Tout = prev_t ? c.T[1 - c.tcur] : nullptr;
     p.newton_cap = learned ? c.ph.newton_maxit_mlp : c.ph.newton_maxit;
+    if (c.d.flatten) {
+      // flags of the stage input, from the same EOS guess the stage uses
+      HIPCHK(h, mhd::launch_shock_flags(c, p.Us, p.Bxs, p.Bys, p.Bzs, p.Tin, p.newton_cap));
+      p.flat = c.shock_f[1];
+    }
     p.bg_cc = c.bg_cc;
     p.bg_fz = c.bg_fz;
     p.heat = c.heat;
@@ -524,6 +547,29 @@ int mhd_get_state(mhd_ctx *h, double *U, double *Bx, double *By, double *Bz, dou
 
 int mhd_sync(mhd_ctx *h) {
   if (!h) return MHD_ERR_ARG;
+  return latched(h);
+}
+
+int mhd_shock_flags(mhd_ctx *h, uint8_t *flags, int32_t where) {
+  if (!h || !flags) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_shock_flags before mhd_set_state");
+  if (!c.d.flatten) return fail(h, MHD_ERR_STATE, "context created without shock flattening");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
+    return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
+  const int s = c.cur;
+  const double *Tg = nullptr;
+  int cap = c.ph.newton_maxit;
+  if (c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T) {
+    Tg = c.T[c.tcur];
+  } else if (c.ph.gasrad) {
+    HIPCHK(h, mhd::launch_mlp_guess(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[0]));
+    Tg = c.T[0];
+    cap = c.ph.newton_maxit_mlp;
+  }
+  HIPCHK(h, mhd::launch_shock_flags(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg, cap));
+  HIPCHK(h, hipMemcpyAsync(flags, c.shock_f[1], c.ncell, kind_out(where), c.stream));
   return latched(h);
 }
 

@@ -62,6 +62,17 @@ __device__ __forceinline__ int xcd_logical_block(int bid, int nblk) {
   return xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
 }
 
+// Cells [c0, c1) of this block of a grid-wide per-cell kernel.  Blocks take
+// contiguous chunks of whole blockDim-cell runs in XCD-contiguous logical
+// order, so the rows and planes a cell's neighbours live in are read by
+// blocks that share one L2.
+__device__ __forceinline__ void block_cells(size_t n, size_t &c0, size_t &c1) {
+  const size_t span = (size_t)gridDim.x * blockDim.x;
+  const size_t per = (n + span - 1) / span * blockDim.x;
+  c0 = (size_t)xcd_logical_block(blockIdx.x, gridDim.x) * per;
+  c1 = c0 + per < n ? c0 + per : n;
+}
+
 // (i, j, k) of a linear cell index q < nx ny nz (< 2^32: three state
 // copies of a larger grid would not fit in HBM), with 32-bit divisions
 __device__ __forceinline__ void cell_ijk(const Phys &ph, size_t q, int &i, int &j, int &k) {
@@ -592,6 +603,60 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   F[1] = fan ? Fs[1] : Fa[1];
 #pragma unroll
   for (int c = 2; c < 7; ++c) F[c] = fan ? (dstar ? Fss[c] : Fs[c]) : Fa[c];
+}
+
+// HLL flux (Harten, Lax & van Leer 1983) in the same deviation form, the
+// solver of faces next to a flattened cell (Sect. 2.7): one state between
+// the fastest waves, with the wave speeds of the LHLLD solver.  U_R - U_L
+// is formed from the deviations, so that no background value is subtracted
+// from another: the thermal energy difference is
+// P_hat (g_L - g_R) i_L i_R + dP_R i_R - dP_L i_L (i = 1/(gamma_e - 1),
+// g = gamma_e deviation) with the gas+radiation EOS, (dP_R - dP_L) i else.
+template <typename R, bool GR>
+__device__ __forceinline__ void hll_flux(const Side<R> &L, const Side<R> &Rt, R bn,
+                                         const FaceBg<R> &bg, R gam, R igm1, R F[7]) {
+  const R rhoL = bg.rho + L.drho, rhoR = bg.rho + Rt.drho;
+  R irL, irR, igL = igm1, igR = igm1;
+  rcp2<R>(rhoL, rhoR, irL, irR);
+  if (GR) rcp2<R>(bg.ge + L.dge - R(1), bg.ge + Rt.dge - R(1), igL, igR);
+  SideQ<R> qL, qR;
+  R cfL, cfR, csL, csR, v2L, v2R;
+  side_prep<R, GR>(L, bn, bg, rhoL, irL, igL, gam, qL, cfL, csL, v2L);
+  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, igR, gam, qR, cfR, csR, v2R);
+  const R cmax = fmax(cfL, cfR);
+  const R SL = fmin(qL.vn, qR.vn) - cmax;
+  const R SR = fmax(qL.vn, qR.vn) + cmax;
+  const R eth = GR ? bg.p * (L.dge - Rt.dge) * igL * igR + Rt.dp * igR - L.dp * igL
+                   : (Rt.dp - L.dp) * igm1;
+  R dU[7];
+  dU[0] = Rt.drho - L.drho;
+  dU[1] = rhoR * Rt.vn - rhoL * L.vn;
+  dU[2] = rhoR * Rt.v1 - rhoL * L.v1;
+  dU[3] = rhoR * Rt.v2 - rhoL * L.v2;
+  dU[4] = eth + R(0.5) * (rhoR * v2R - rhoL * v2L) +
+          R(0.5) * ((Rt.b1 * Rt.b1 + Rt.b2 * Rt.b2) - (L.b1 * L.b1 + L.b2 * L.b2));
+  dU[5] = Rt.b1 - L.b1;
+  dU[6] = Rt.b2 - L.b2;
+  const R iw = rcp<R>(SR - SL);
+  const bool outL = R(0) <= SL, outR = SR < R(0);
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    const R fh = (SR * qL.F[c] - SL * qR.F[c] + SL * SR * dU[c]) * iw;
+    F[c] = outL ? qL.F[c] : (outR ? qR.F[c] : fh);
+  }
+}
+
+// Face flux: HLL where the face touches a flattened cell, LHLLD elsewhere.
+// The two solvers run under a lane mask, so their registers are not live
+// at the same time.
+template <typename R, bool GR>
+__device__ __forceinline__ void face_flux(bool hll, const Side<R> &L, const Side<R> &Rt, R bn,
+                                          const FaceBg<R> &bg, R gam, R igm1, int xi_mode,
+                                          R mcut, R imcut, R F[7]) {
+  if (hll)
+    hll_flux<R, GR>(L, Rt, bn, bg, gam, igm1, F);
+  else
+    riemann<R, GR>(L, Rt, bn, bg, gam, igm1, xi_mode, mcut, imcut, F);
 }
 
 // ---------------------------------------------------------------------------

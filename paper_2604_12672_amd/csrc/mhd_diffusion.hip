@@ -62,16 +62,6 @@ __device__ __forceinline__ double diff_rhs(const Phys &ph, const DiffParams &dp,
   return div * rcp<double>(rho[q]);
 }
 
-// Cells [c0, c1) of this block.  Blocks take contiguous chunks of whole
-// 256-cell runs in XCD-contiguous logical order, so the rows and planes a
-// cell's neighbours live in are read by blocks that share one L2.
-__device__ __forceinline__ void block_cells(size_t n, size_t &c0, size_t &c1) {
-  const size_t span = (size_t)gridDim.x * blockDim.x;
-  const size_t per = (n + span - 1) / span * blockDim.x;
-  c0 = (size_t)xcd_logical_block(blockIdx.x, gridDim.x) * per;
-  c1 = c0 + per < n ? c0 + per : n;
-}
-
 // e_int, T (Newton from Tg, or the bracketed solve), c_v and chi of every
 // cell of the state
 __global__ __launch_bounds__(256) void diff_init_kernel(

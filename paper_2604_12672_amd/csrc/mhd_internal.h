@@ -52,6 +52,7 @@ struct StagePtrs {
   const double *heat, *force;          // nullable
   const double *dt_dev;                // device dt (nullable: use dt_host)
   int newton_cap;                      // Newton steps before the bracketed solve
+  const uint8_t *flat = nullptr;       // shock-flattening flags [n] (nullable)
   int *flags;                          // latched error flags
   unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
 };
@@ -100,6 +101,10 @@ struct Ctx {
   DiffParams dparams{};
   bool have_opacity = false;
   DiffBufs diff;
+  // shock flattening: thermal pressure of the stage input and two byte
+  // planes for the detector and its dilation (allocated when enabled)
+  double *shock_p = nullptr;
+  uint8_t *shock_f[2] = {nullptr, nullptr};
   int zseg = 32;
   std::string err;
 };
@@ -133,6 +138,10 @@ hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, cons
 hipError_t launch_parabolic_dt(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz, const double *Tg,
                                double *dtp_dev);
+// shock-flattening flags of a stage input (mhd_flatten.hip); the flags end
+// in c.shock_f[1]
+hipError_t launch_shock_flags(const Ctx &c, const double *U, const double *Bx, const double *By,
+                              const double *Bz, const double *Tg, int newton_cap);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0,
                             bool stats);

@@ -256,6 +256,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   __shared__ R sRZ[NTHREADS];       // cell reference E_z of plane k+1
   __shared__ R sEZ[2][NTHREADS];    // edge E_z, planes by parity
   __shared__ R sEX[NTHREADS];       // edge E_x(k+1/2)
+  __shared__ int sFL[NTHREADS];     // flattening flag of cell k+1
 
   const int tid = threadIdx.x;
   const int tx = tid % TT, ty = tid / TT;
@@ -336,6 +337,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   R xf_ey_prev = 0, xf_m_prev = 0;  // own x-face E_y and mass flux, plane k
   R yf_ex_prev = 0, yf_m_prev = 0;  // own y-face E_x and mass flux, plane k
   R rx_prev = 0, ry_prev = 0;       // own cell reference E_x, E_y, plane k
+  // shock-flattening flags of the own column's cells k and k+1 (Sect. 2.7):
+  // a flagged cell is reconstructed with van Leer, and every face it
+  // touches takes the HLL flux
+  int fk = 0, fc = 0;
   unsigned long long nit = 0, nmax = 0, nfb = 0;
   int bad = 0;
 #pragma unroll
@@ -391,10 +396,12 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     R zf_ey = 0, zf_ex = 0, zf_m = 0;
     Side<R> xl{}, xll{}, yl{};
     R rx = 0, ry = 0, rz = 0;
+    int fn = 0;  // flag of cell k+2 (a mirror image carries its source's)
     {
       const int q = k + 2;
       int mir;
       const int kk = zsource(ph, q, mir);
+      if (p.flat) fn = p.flat[(size_t)kk * plane + colq];
       R *sWn = &sW[q & 1][0][0];
       CellLoad c, rc;
       if (PREFETCH) {
@@ -447,7 +454,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       }
       if (k >= z0 - 2) {
         Side<R> botn, topn;
-        recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn, pph);
+        const bool pphc = pph && !fc;
+        recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn, pphc);
         if (k >= z0 - 1) {
           const int fzi = zface(ph, k + 1);
           FaceBg<R> bgf;
@@ -459,7 +467,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           bzf = p.Bzs[(size_t)fzi * plane + colq];
           const R bzn = (R)bzf;
           R fz[7];
-          riemann<R, GR>(topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut, imcut, fz);
+          face_flux<R, GR>((fk | fc) != 0, topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut,
+                           imcut, fz);
           to_cons<R>(2, fz, fzc);
           zf_ey = -fz[5];  // z-face E_y = -F_z[B_x]
           zf_ex = fz[6];   // z-face E_x = +F_z[B_y]
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           b[f] = sWc[f * LP + lw_own + 1];
         }
         Side<R> xh;
-        recon_cell<R, GR>(0, a, Wc, b, xl, xh, pph);
+        recon_cell<R, GR>(0, a, Wc, b, xl, xh, pphc);
         xll = side_from_left<R>(xh);  // L state of the x-face ci-1/2
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -486,8 +495,9 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           b[f] = sWc[f * LP + lw_own + LW];
         }
         Side<R> yh;
-        recon_cell<R, GR>(1, a, Wc, b, yl, yh, pph);
+        recon_cell<R, GR>(1, a, Wc, b, yl, yh, pphc);
         side_store<R, GR>(sYR, tid, yh);
+        sFL[tid] = fc;
         // cell reference EMF -(v x B) of plane k+1
         rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);
         ry = -(Wc[Q_VZ] * Wc[Q_BX] - Wc[Q_VX] * Wc[Q_BZ]);
@@ -507,9 +517,11 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       bgc.p = (R)sBc[1][jc];
       bgc.ge = (R)sBc[2][jc];
       bgc.gc = (R)sBc[3][jc];
-      riemann<R, GR>(xll, xl, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
+      const bool hx = (fc | dpp_shr1(fc)) != 0;  // cells ci-1 and ci
+      face_flux<R, GR>(hx, xll, xl, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
       const Side<R> yll = side_load<R, GR>(sYR, tdn);
-      riemann<R, GR>(yll, yl, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
+      const bool hy = (fc | sFL[tdn]) != 0;  // cells cj-1 and cj
+      face_flux<R, GR>(hy, yll, yl, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
       R fyc[5];
       to_cons<R>(1, fy, fyc);
 #pragma unroll
@@ -627,6 +639,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     for (int f = 0; f < NF; ++f) Wc[f] = Wn[f];
     bxf_c = bxf_n;
     byf_c = byf_n;
+    fk = fc;
+    fc = fn;
   }
   if (bad) atomicOr(p.flags, bad);
   if (GR) {

@@ -43,7 +43,8 @@ class GridDesc(C.Structure):
         ("rgas", C.c_double), ("arad", C.c_double), ("grav", C.c_double * 3),
         ("rk_order", C.c_int32), ("precision", C.c_int32), ("eos_guess", C.c_int32),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("mach_cut", C.c_double),
-        ("xi_mode", C.c_int32), ("recon", C.c_int32),
+        ("xi_mode", C.c_int32), ("recon", C.c_int32), ("flatten", C.c_int32),
+        ("eps_sf", C.c_double),
     ]
 
 
@@ -58,6 +59,7 @@ class Diag(C.Structure):
 EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eos_mlp",
            "mhd_eos_solve", "mhd_set_state", "mhd_compute_dt", "mhd_step", "mhd_advance",
            "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
+           "mhd_shock_flags",
            "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse"]
 
 _lib = None
@@ -88,6 +90,7 @@ def load():
     L.mhd_advance.argtypes = [vp, C.c_double, C.c_int32]
     L.mhd_get_state.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
     L.mhd_sync.argtypes = [vp]
+    L.mhd_shock_flags.argtypes = [vp, vp, C.c_int32]
     L.mhd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
     L.mhd_last_error.argtypes = [vp]
     L.mhd_last_error.restype = C.c_char_p
@@ -126,6 +129,8 @@ def make_desc(params: dict, precision=PREC_FP64, eos_guess=GUESS_PREV_T) -> Grid
     d.mach_cut = float(p.get("mach_cut", 0.6))
     d.xi_mode = int(p.get("xi_mode", 0))
     d.recon = int(p.get("recon", RECON_VANLEER))
+    d.flatten = int(p.get("flatten", 0))
+    d.eps_sf = float(p.get("eps_sf", 0.2))
     return d
 
 
@@ -298,6 +303,23 @@ class Grid:
         self._check_shapes(out["U"], out["Bx"], out["By"], out["Bz"], T)
         self._check(self._L.mhd_get_state(self._h, _ptr(out["U"], w), _ptr(out["Bx"], w),
                                           _ptr(out["By"], w), _ptr(out["Bz"], w), _ptr(T, w), w))
+        return out
+
+    def shock_flags(self, out=None):
+        """Shock-flattening flags of the current state (uint8 per cell), into
+        `out` (a uint8 numpy array or CUDA tensor of the grid's shape) or a
+        new numpy array."""
+        if out is None:
+            out = np.empty(self.shape, dtype=np.uint8)
+        if _is_torch(out):
+            import torch
+            assert out.is_cuda and out.dtype == torch.uint8 and out.is_contiguous()
+            assert tuple(out.shape) == self.shape
+            ptr, w = C.c_void_p(out.data_ptr()), DEVICE
+        else:
+            assert out.dtype == np.uint8 and out.flags["C_CONTIGUOUS"] and out.shape == self.shape
+            ptr, w = out.ctypes.data_as(C.c_void_p), HOST
+        self._check(self._L.mhd_shock_flags(self._h, ptr, w))
         return out
 
     def diagnostics(self):

@@ -510,12 +510,16 @@ def config(idx: int, n: int | None = None):
     raise ValueError(idx)
 
 
-def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2, eos=EOS_IDEAL):
+def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2, eos=EOS_IDEAL,
+               blast=None):
     """Smooth random state on [0,1]^3 (parity tests on ragged grids): rho and
     P = 1 + 0.2 x (sum of a few low Fourier modes), v likewise with
     amplitude amp_v, face B from a random edge vector potential (amplitude
     amp_b) so that div B = 0 to round-off.  With a reflecting z the vector
-    potential's x/y components vanish on the walls."""
+    potential's x/y components vanish on the walls.  blast = (factor,
+    radius): the thermal pressure is raised by that factor inside a sphere
+    about the box centre (gas+radiation: T by factor^(1/4)), a pressure
+    jump for the shock-flattening tests."""
     if eos == EOS_GASRAD:
         p = gasrad_params(nx, ny, nz, bcz=bcz)
     else:
@@ -536,6 +540,10 @@ def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2
     rho = 1.0 + np.abs(field(0.2)) + 0.05
     P = 1.0 + np.abs(field(0.2)) + 0.05
     v = [field(amp_v) for _ in range(3)]
+    inside = None
+    if blast is not None:
+        inside = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2 < blast[1] ** 2
+        P = np.where(inside, P * blast[0], P)
     if bcz == BC_REFLECT:
         v[2] *= np.sin(np.pi * Z)
     nzf = nz + 1 if bcz == BC_REFLECT else nz
@@ -579,6 +587,8 @@ def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2
     if eos == EOS_GASRAD:
         T = 10.0 ** (6.0 + field(1.0))
         rho = 10.0 ** field(1.0)
+        if inside is not None:
+            T = np.where(inside, T * blast[0] ** 0.25, T)
         P, eint = gasrad_forward(p, rho, T)
         cs = np.sqrt(P.mean() / rho.mean())
         v = [vv * cs for vv in v]

@@ -53,7 +53,7 @@ int main(void) {
   O(mhd_grid_desc, lo); O(mhd_grid_desc, bc); O(mhd_grid_desc, eos);
   O(mhd_grid_desc, gamma); O(mhd_grid_desc, grav); O(mhd_grid_desc, rk_order);
   O(mhd_grid_desc, newton_tol); O(mhd_grid_desc, mach_cut); O(mhd_grid_desc, xi_mode);
-  O(mhd_grid_desc, recon);
+  O(mhd_grid_desc, recon); O(mhd_grid_desc, flatten); O(mhd_grid_desc, eps_sf);
   O(mhd_diag, total); O(mhd_diag, newton_iters); O(mhd_diag, error_flags);
   return 0;
 }
@@ -82,7 +82,8 @@ def _desc(**kw):
     dict(nx=0), dict(nz=-3), dict(gamma=1.0), dict(bcz=7), dict(rk_order=4),
     dict(eos=5), dict(hi=(1.0, 0.0, 1.0)), dict(bcz=1, nz=1),
     dict(eos=1, rgas=0.0), dict(xi_mode=9), dict(mach_cut=0.0),
-    dict(nx=2048, ny=2048, nz=1024), dict(recon=4),
+    dict(nx=2048, ny=2048, nz=1024), dict(recon=4), dict(flatten=2),
+    dict(flatten=1, eps_sf=0.0), dict(flatten=1, eps_sf=float("nan")),
 ])
 def test_descriptor_validation(lib, bad):
     d = _desc(**bad)

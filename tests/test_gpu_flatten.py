@@ -1,0 +1,170 @@
+"""Shock flattening (Sect. 2.7) on the GPU against the oracle, through the C
+ABI: the flags themselves bit for bit (a byte per cell), and flattened steps
+(van Leer and PPH reconstruction, SSP-RK2 and RK3, periodic and walled
+boxes, ideal gas and gas + radiation, FP64 and split precision).
+
+Inputs: the smooth random boxes of the other parity tests with the thermal
+pressure raised tenfold inside a sphere (about half the cells flagged), the
+Brio-Wu tube along each axis, and the gas + radiation box (every cell
+flagged: its temperature varies by a decade between neighbours).
+
+The flag is an integer decided in FP64 from the pressure on both sides;
+the pressures agree to rounding, so a flag could only differ for a cell
+whose detector ratio lies within rounding of 1, which these inputs do not
+produce.  Tolerances of the states are those of the unflattened tests:
+rel L2 <= 1e-10 (FP64), <= 1e-5 (split), momentum and field components
+relative to their vector's norm."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2604_12672_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = [("U", 0, "rho"), ("U", 1, "m_x"), ("U", 2, "m_y"), ("U", 3, "m_z"), ("U", 4, "E"),
+          ("Bx", None, "B_x"), ("By", None, "B_y"), ("Bz", None, "B_z")]
+
+
+@pytest.fixture(scope="module")
+def mhd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_12672_amd import mhd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2604_12672_amd import build
+        build.build()
+    m.load()
+    return m
+
+
+def rel_errors(out, ref):
+    """L2 error of each component over the L2 norm of its vector (momentum
+    and field components share their vector's norm: a component that is
+    zero in exact arithmetic, such as B_z of a tube along x, carries only
+    rounding noise on both sides)."""
+    def norm2(a):
+        return float(np.sum(a * a))
+    vec = {"m": sum(norm2(ref["U"][c]) for c in (1, 2, 3)),
+           "B": sum(norm2(ref[k]) for k in ("Bx", "By", "Bz"))}
+    errs = {}
+    for key, c, name in FIELDS:
+        a = out[key] if c is None else out[key][c]
+        b = ref[key] if c is None else ref[key][c]
+        den = vec["m"] if name.startswith("m_") else vec["B"] if name.startswith("B_") \
+            else norm2(b)
+        num = math.sqrt(norm2(a - b))
+        errs[name] = num / math.sqrt(den) if den > 0 else num
+    return errs
+
+
+def _with(w, **kw):
+    return wl.Workload(w.name, dict(w.params, **kw), w.U, w.Bx, w.By, w.Bz, T=w.T,
+                       bg_cc=w.bg_cc, bg_fz=w.bg_fz, heat=w.heat, force=w.force, cfl=w.cfl)
+
+
+def run_pair(mhd, w, nsteps, precision=0, cfl=None):
+    print(f"case {w.name} {w.shape} {w.params.get('recon')} rk{w.params.get('rk_order')} "
+          f"steps={nsteps} prec={precision}", flush=True)
+    cfl = cfl or w.cfl
+    o = orc.Oracle(w.params, **w.extras())
+    ref = w.state()
+    dts = []
+    for _ in range(nsteps):
+        dt = o.compute_dt(ref, cfl)
+        o.step(ref, dt)
+        dts.append(dt)
+    g = mhd.Grid(w.params, precision=precision)
+    g.load(w)
+    for dt in dts:
+        g.step(dt)
+    out = g.get_state(with_T=w.T is not None)
+    flags = g.shock_flags()
+    diag = g.diagnostics()
+    g.close()
+    return out, ref, diag, o.shock_flags(ref), flags
+
+
+def _blast(shape, bcz, eos=wl.EOS_IDEAL, **kw):
+    w = wl.smooth_box(*shape, bcz=bcz, eos=eos, blast=(10.0, 0.25))
+    return _with(w, flatten=1, **kw)
+
+
+@pytest.mark.parametrize("shape,bcz,eos", [((20, 17, 13), 0, 0), ((19, 15, 14), 1, 0),
+                                           ((33, 6, 5), 0, 0), ((12, 11, 10), 1, 1),
+                                           ((1, 24, 9), 0, 0)])
+def test_flags_match_oracle(mhd, shape, bcz, eos):
+    w = _blast(shape, bcz, eos)
+    print(f"case flags {shape} bcz={bcz} eos={eos}", flush=True)
+    ref = orc.Oracle(w.params, **w.extras()).shock_flags(w.state())
+    g = mhd.Grid(w.params)
+    g.load(w)
+    got = g.shock_flags()
+    g.close()
+    assert 0 < ref.sum() and np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_brio_wu_flags_and_pph_rk3_steps(mhd, axis):
+    """Brio-Wu along each axis with PPH, SSP-RK3 and flattening, 60 steps:
+    flags and state against the oracle."""
+    w = _with(wl.brio_wu(200, axis=axis), flatten=1, recon=orc.RECON_PPH, rk_order=3)
+    out, ref, diag, fref, fgot = run_pair(mhd, w, 60)
+    assert np.array_equal(fgot, fref) and fref.sum() > 0
+    errs = rel_errors(out, ref)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+
+
+@pytest.mark.parametrize("shape,bcz", [((20, 17, 13), 0), ((19, 15, 14), 1)])
+@pytest.mark.parametrize("recon,rk", [(orc.RECON_VANLEER, 2), (orc.RECON_PPH, 3)])
+def test_flattened_steps_fp64(mhd, shape, bcz, recon, rk):
+    w = _blast(shape, bcz, recon=recon, rk_order=rk)
+    out, ref, diag, fref, fgot = run_pair(mhd, w, 3)
+    assert np.array_equal(fgot, fref)
+    errs = rel_errors(out, ref)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert diag["divb_max"] < 1e-12
+
+
+@pytest.mark.parametrize("shape,bcz", [((20, 17, 13), 0), ((19, 15, 14), 1)])
+@pytest.mark.parametrize("recon,rk", [(orc.RECON_VANLEER, 2), (orc.RECON_PPH, 3)])
+def test_flattened_steps_split(mhd, shape, bcz, recon, rk):
+    w = _blast(shape, bcz, recon=recon, rk_order=rk)
+    out, ref, diag, fref, fgot = run_pair(mhd, w, 3, precision=1)
+    errs = rel_errors(out, ref)
+    assert all(v <= 1e-5 for v in errs.values()), errs
+    assert diag["divb_max"] < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-5)])
+def test_flattened_gasrad(mhd, precision, tol):
+    w = _blast((12, 11, 10), 0, eos=wl.EOS_GASRAD, recon=orc.RECON_PPH, rk_order=3)
+    out, ref, diag, fref, fgot = run_pair(mhd, w, 2, precision=precision)
+    errs = rel_errors(out, ref)
+    assert all(v <= tol for v in errs.values()), errs
+    if precision == 0:
+        assert np.array_equal(fgot, fref)
+
+
+def test_flattened_box_across_tiles_and_segments(mhd):
+    """96^3 blast box: 7 x 7 tiles of 14 columns with a ragged last tile and
+    several z segments, PPH + SSP-RK3, one step against the full oracle."""
+    w = _blast((96, 96, 96), 0, recon=orc.RECON_PPH, rk_order=3)
+    out, ref, diag, fref, fgot = run_pair(mhd, w, 1)
+    assert np.array_equal(fgot, fref)
+    assert 0.01 < fref.mean() < 0.5
+    errs = rel_errors(out, ref)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+
+
+def test_flags_need_flattening_enabled(mhd):
+    w = wl.smooth_box(8, 8, 8)
+    g = mhd.Grid(w.params)
+    g.load(w)
+    with pytest.raises(mhd.MHDError):
+        g.shock_flags()
+    g.close()
