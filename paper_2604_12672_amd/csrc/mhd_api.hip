@@ -298,9 +298,8 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   if (desc->flatten) {
     if ((e = hipMalloc(&c.shock_p, sizeof(double) * c.ncell)) != hipSuccess)
       return cleanup(e, "hipMalloc shock pressure");
-    for (int i = 0; i < 2; ++i)
-      if ((e = hipMalloc(&c.shock_f[i], c.ncell)) != hipSuccess)
-        return cleanup(e, "hipMalloc shock flags");
+    if ((e = hipMalloc(&c.shock_f, c.ncell)) != hipSuccess)
+      return cleanup(e, "hipMalloc shock flags");
   }
   if ((e = hipMemsetAsync(c.flags, 0, sizeof(int), c.stream)) != hipSuccess)
     return cleanup(e, "hipMemset flags");
@@ -333,8 +332,7 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.nstats);
   (void)hipFree(c.mlp);
   (void)hipFree(c.shock_p);
-  (void)hipFree(c.shock_f[0]);
-  (void)hipFree(c.shock_f[1]);
+  (void)hipFree(c.shock_f);
   mhd::DiffBufs &d = c.diff;
   (void)hipFree(d.e0);
   for (int i = 0; i < 3; ++i) (void)hipFree(d.y[i]);
@@ -450,15 +448,19 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     const bool learned = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP;
     if (learned) {
       // learned guesses of the stage input, polished by Newton in the stage
-      HIPCHK(h, mhd::launch_mlp_guess(c, p.Us, p.Bxs, p.Bys, p.Bzs, c.T[0]));
+      // (with flattening already here, where the pressure is taken too)
+      HIPCHK(h, mhd::launch_mlp_guess(c, p.Us, p.Bxs, p.Bys, p.Bzs, c.T[0],
+                                      c.d.flatten ? c.shock_p : nullptr));
     }
     p.Tin = prev_t ? c.T[c.tcur] : (learned ? c.T[0] : nullptr);
     p.Tout = prev_t ? c.T[1 - c.tcur] : nullptr;
     p.newton_cap = learned ? c.ph.newton_maxit_mlp : c.ph.newton_maxit;
     if (c.d.flatten) {
       // flags of the stage input, from the same EOS guess the stage uses
-      HIPCHK(h, mhd::launch_shock_flags(c, p.Us, p.Bxs, p.Bys, p.Bzs, p.Tin, p.newton_cap));
-      p.flat = c.shock_f[1];
+      if (!learned)
+        HIPCHK(h, mhd::launch_shock_pressure(c, p.Us, p.Bxs, p.Bys, p.Bzs, p.Tin, p.newton_cap));
+      HIPCHK(h, mhd::launch_shock_flags(c));
+      p.flat = c.shock_f;
     }
     p.bg_cc = c.bg_cc;
     p.bg_fz = c.bg_fz;
@@ -559,17 +561,13 @@ int mhd_shock_flags(mhd_ctx *h, uint8_t *flags, int32_t where) {
   if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   const int s = c.cur;
-  const double *Tg = nullptr;
-  int cap = c.ph.newton_maxit;
-  if (c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T) {
-    Tg = c.T[c.tcur];
-  } else if (c.ph.gasrad) {
-    HIPCHK(h, mhd::launch_mlp_guess(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[0]));
-    Tg = c.T[0];
-    cap = c.ph.newton_maxit_mlp;
-  }
-  HIPCHK(h, mhd::launch_shock_flags(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], Tg, cap));
-  HIPCHK(h, hipMemcpyAsync(flags, c.shock_f[1], c.ncell, kind_out(where), c.stream));
+  if (c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP)
+    HIPCHK(h, mhd::launch_mlp_guess(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[0], c.shock_p));
+  else
+    HIPCHK(h, mhd::launch_shock_pressure(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s],
+                                         c.ph.gasrad ? c.T[c.tcur] : nullptr, c.ph.newton_maxit));
+  HIPCHK(h, mhd::launch_shock_flags(c));
+  HIPCHK(h, hipMemcpyAsync(flags, c.shock_f, c.ncell, kind_out(where), c.stream));
   return latched(h);
 }
 

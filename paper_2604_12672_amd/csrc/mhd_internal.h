@@ -101,10 +101,10 @@ struct Ctx {
   DiffParams dparams{};
   bool have_opacity = false;
   DiffBufs diff;
-  // shock flattening: thermal pressure of the stage input and two byte
-  // planes for the detector and its dilation (allocated when enabled)
+  // shock flattening: thermal pressure of the stage input and the flags
+  // (one byte per cell), allocated when enabled
   double *shock_p = nullptr;
-  uint8_t *shock_f[2] = {nullptr, nullptr};
+  uint8_t *shock_f = nullptr;
   int zseg = 32;
   std::string err;
 };
@@ -125,8 +125,10 @@ hipError_t launch_zero_walls(const Ctx &c, double *Bz);
 size_t mlp_bytes();
 // resident stage blocks per CU for the context's kernel variant (>= 1)
 int stage_blocks_per_cu(const Ctx &c);
+// learned guesses into Tg; with P (nullable) also Newton-polished there and
+// the thermal pressure into P
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, double *Tg);
+                            const double *Bz, double *Tg, double *P = nullptr);
 hipError_t launch_diff_init(const Ctx &c, const double *U, const double *Bx, const double *By,
                             const double *Bz, const double *Tg);
 hipError_t launch_diff_stage(const Ctx &c, const double *U, const double *Ta, const double *chia,
@@ -138,10 +140,12 @@ hipError_t launch_diff_finish(const Ctx &c, double *U, const double *ylast, cons
 hipError_t launch_parabolic_dt(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz, const double *Tg,
                                double *dtp_dev);
-// shock-flattening flags of a stage input (mhd_flatten.hip); the flags end
-// in c.shock_f[1]
-hipError_t launch_shock_flags(const Ctx &c, const double *U, const double *Bx, const double *By,
-                              const double *Bz, const double *Tg, int newton_cap);
+// shock flattening (mhd_flatten.hip): the thermal pressure of a stage input
+// into c.shock_p, then the flags from it into c.shock_f
+hipError_t launch_shock_pressure(const Ctx &c, const double *U, const double *Bx,
+                                 const double *By, const double *Bz, const double *Tg,
+                                 int newton_cap);
+hipError_t launch_shock_flags(const Ctx &c);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0,
                             bool stats);

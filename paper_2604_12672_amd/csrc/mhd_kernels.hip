@@ -884,12 +884,17 @@ hipError_t launch_init_temperature(const Ctx &c, const double *U,
 // learned mode): the stage kernel reads it as its temperature guess
 // ---------------------------------------------------------------------------
 
+// With P != nullptr (shock flattening) the guess is polished by Newton
+// right here and the converged temperature is stored in its place, together
+// with the thermal pressure the flattening detector needs: the stage input
+// is then read once for both, and the stage's own Newton starts converged.
 __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *__restrict__ U,
                                                         const double *__restrict__ Bx,
                                                         const double *__restrict__ By,
                                                         const double *__restrict__ Bz,
                                                         const void *mlp,
-                                                        double *__restrict__ Tg) {
+                                                        double *__restrict__ Tg,
+                                                        double *__restrict__ P, int *flags) {
   __shared__ __attribute__((aligned(16))) char sMlpRaw[sizeof(MlpLds)];
   const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
   stage_mlp(mlp, sMlpRaw, threadIdx.x, 256);
@@ -932,18 +937,29 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
     if (base + stride < n)
       fetch(base + stride + threadIdx.x < n ? base + stride + threadIdx.x : n - 1, un, fn);
     float x0, x1;
-    mlp_inputs(ph, u[0], specific_eint(u, b), x0, x1);
+    const double e = specific_eint(u, b);
+    mlp_inputs(ph, u[0], e, x0, x1);
     const double t = mlp_guess_wave(ph, sMlp, x0, x1, lane);
-    if (valid) Tg[q] = t;
+    if (!valid) continue;
+    if (!P) {
+      Tg[q] = t;
+      continue;
+    }
+    const double zero_bg[4] = {0.0, 0.0, 0.0, 0.0};
+    PrimOut o;
+    cons2prim<true>(ph, u, b, t, zero_bg, o, ph.newton_maxit_mlp);
+    if (o.bad) atomicOr(flags, o.bad);
+    Tg[q] = o.T;
+    P[q] = o.w[Q_P];  // full pressure: the background passed is zero
   }
 }
 
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, double *Tg) {
+                            const double *Bz, double *Tg, double *P) {
   long long nb = (long long)((c.ncell + 255) / 256);
   nb = nb < 8192 ? nb : 8192;
   hipLaunchKernelGGL(mlp_guess_kernel, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph, U, Bx,
-                     By, Bz, c.mlp, Tg);
+                     By, Bz, c.mlp, Tg, P, c.flags);
   return hipGetLastError();
 }
 

@@ -89,16 +89,19 @@ def run_pair(mhd, w, nsteps, precision=0, cfl=None):
     return out, ref, diag, o.shock_flags(ref), flags
 
 
-def _blast(shape, bcz, eos=wl.EOS_IDEAL, **kw):
-    w = wl.smooth_box(*shape, bcz=bcz, eos=eos, blast=(10.0, 0.25))
+def _blast(shape, bcz, eos=wl.EOS_IDEAL, radius=0.25, **kw):
+    w = wl.smooth_box(*shape, bcz=bcz, eos=eos, blast=(10.0, radius))
     return _with(w, flatten=1, **kw)
 
 
 @pytest.mark.parametrize("shape,bcz,eos", [((20, 17, 13), 0, 0), ((19, 15, 14), 1, 0),
                                            ((33, 6, 5), 0, 0), ((12, 11, 10), 1, 1),
-                                           ((1, 24, 9), 0, 0)])
+                                           ((1, 24, 9), 0, 0), ((70, 5, 2), 1, 0),
+                                           ((9, 9, 70), 0, 0), ((131, 10, 3), 1, 0)])
 def test_flags_match_oracle(mhd, shape, bcz, eos):
-    w = _blast(shape, bcz, eos)
+    """Flag tiles are 64 x 4 columns by 32 planes: ragged tiles in x and y,
+    several z segments, walls two and three planes apart."""
+    w = _blast(shape, bcz, eos, radius=0.3)
     print(f"case flags {shape} bcz={bcz} eos={eos}", flush=True)
     ref = orc.Oracle(w.params, **w.extras()).shock_flags(w.state())
     g = mhd.Grid(w.params)
@@ -168,3 +171,32 @@ def test_flags_need_flattening_enabled(mhd):
     with pytest.raises(mhd.MHDError):
         g.shock_flags()
     g.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_flattened_with_learned_guess(mhd, precision, tol):
+    """Gas + radiation blast box with the learned guess: the guess kernel also
+    polishes the temperature and takes the pressure for the detector."""
+    from paper_2604_12672_amd import eos_mlp
+    model = eos_mlp.MLPGuess.load()
+    w = _blast((18, 15, 12), 1, eos=wl.EOS_GASRAD, radius=0.3)
+    print(f"case learned flattened prec={precision}", flush=True)
+    o = orc.Oracle(w.params, **w.extras())
+    fref0 = o.shock_flags(w.state())
+    ref = w.state()
+    dts = []
+    for _ in range(2):
+        dt = o.compute_dt(ref, w.cfl)
+        o.step(ref, dt)
+        dts.append(dt)
+    g = mhd.Grid(w.params, precision=precision, eos_guess=mhd.GUESS_MLP)
+    g.load(w, mlp=model)
+    assert np.array_equal(g.shock_flags(), fref0)
+    for dt in dts:
+        g.step(dt)
+    out = g.get_state()
+    diag = g.diagnostics()
+    g.close()
+    errs = rel_errors(out, ref)
+    assert all(v <= tol for v in errs.values()), errs
+    assert diag["divb_max"] < 1e-12 and diag["fallbacks"] == 0
