@@ -392,13 +392,35 @@ def turbulence_bench(mhd, model, args):
     return t, tflat
 
 
+def blast_bench(mhd, n, steps, warmup):
+    """A pressure-jump box with flattening active where it matters: the
+    smooth random box with the pressure raised tenfold in a sphere of radius
+    0.25, PPH + SSP-RK3 at CFL 0.4, shock flattening on, FP64 and split."""
+    from paper_2604_12672_amd import workloads as wl
+    log(f"bench: flattened blast box {n}^3")
+    w = wl.smooth_box(n, n, n, blast=(10.0, 0.25))
+    w.params = dict(w.params, flatten=1, recon=mhd.RECON_PPH, rk_order=3)
+    w.cfl = 0.4
+    res = {}
+    for name, prec in (("fp64", mhd.PREC_FP64), ("split", mhd.PREC_SPLIT)):
+        r = gpu_run(mhd, w, prec, steps, warmup)
+        res[name] = {"value": round(r["value"], 1), "ms_per_step": round(r["ms"], 4),
+                     "flagged_fraction_at_end": round(r["flagged"], 5),
+                     "divb_max": r["diag"]["divb_max"]}
+        log(f"bench: blast {name} {r['ms']:.3f} ms/step, flagged {r['flagged']:.4f}")
+    res["workload"] = (f"smooth random MHD box {n}^3 with a tenfold pressure sphere "
+                       f"(r = 0.25), PPH + SSP-RK3, CFL 0.4, shock flattening")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="linear grid size of the headline box")
-    ap.add_argument("--only", choices=["fp64", "split", "rkl2", "turbulence"], default=None,
+    ap.add_argument("--only", choices=["fp64", "split", "rkl2", "turbulence", "blast"],
+                    default=None,
                     help="run only this path of the headline box, or only the RKL2 "
                          "diffusion or the turbulence measurement (profiling)")
     ap.add_argument("--no-extras", action="store_true",
@@ -430,6 +452,10 @@ def main():
     if args.only == "turbulence":
         t, tf = turbulence_bench(mhd, eos_mlp.MLPGuess.load(), args)
         print(json.dumps({"turbulence": t, "turbulence_flattened": tf}), flush=True)
+        return
+    if args.only == "blast":
+        print(json.dumps({"blast_flattened": blast_bench(mhd, n, args.steps, args.warmup)}),
+              flush=True)
         return
     if args.only == "rkl2":
         print(json.dumps({"rkl2_diffusion": rkl2_bench(mhd, n),
@@ -531,6 +557,7 @@ def main():
         log(f"bench: split error {out['split_error']['rel_l2_vs_fp64']}")
         out["turbulence"], out["turbulence_flattened"] = turbulence_bench(mhd, model, args)
     if not args.no_extras and not args.only:
+        out["blast_flattened"] = blast_bench(mhd, args.n, args.steps, args.warmup)
         out["rkl2_diffusion"] = rkl2_bench(mhd, args.n)
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle) {args.cpu_n}^3")
