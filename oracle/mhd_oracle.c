@@ -207,6 +207,38 @@ void orc_pph(double wm, double wc, double wp, double *lo, double *hi) {
   *lo = (2.0 * wm + 5.0 * wc - wp) / 6.0;
 }
 
+/* READING: the paper reconstructs mass fractions with a limited parabola in
+   PPH mode and cites the limiter; here each face value of the three-cell
+   parabola is first bounded by the two averages beside that face, then the
+   parabola is made monotone inside the cell with the constraints of
+   Colella & Woodward (1984): a cell holding a local extremum is flat, and a
+   face value that would make the parabola overshoot inside the cell is
+   moved so the parabola's extremum sits at the opposite face. */
+static double clamp2(double v, double a, double b) {
+  const double lo = a < b ? a : b, hi = a < b ? b : a;
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+void orc_pph_limited(double wm, double wc, double wp, double *lo, double *hi) {
+  double l, h;
+  orc_pph(wm, wc, wp, &l, &h);
+  l = clamp2(l, wm, wc);
+  h = clamp2(h, wc, wp);
+  if ((h - wc) * (wc - l) <= 0.0) {
+    l = wc;
+    h = wc;
+  } else {
+    const double d = h - l;
+    const double m6 = 6.0 * (wc - 0.5 * (l + h));
+    if (d * m6 > d * d)
+      l = 3.0 * wc - 2.0 * h;
+    else if (-d * d > d * m6)
+      h = 3.0 * wc - 2.0 * l;
+  }
+  *lo = l;
+  *hi = h;
+}
+
 /* ------------------------------------------------------------------ */
 /* HLLD / LHLLD Riemann solver (Sect. 2.6; Miyoshi & Kusano 2005)       */
 /* ------------------------------------------------------------------ */
@@ -622,8 +654,12 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
   const double dxs[3] = {c->dx, c->dy, c->dz};
   int err = ORC_OK;
 
-  /* steps 1-2: primitives and their deviation from the background */
+  /* steps 1-2: primitives and their deviation from the background; the
+     mass fractions X_l = (rho X_l) / rho of the passive species */
+  const int nsp = c->nspecies;
+  if (nsp < 0 || nsp > 64) return ORC_ERR_ARG;
   double *dW = (double *)malloc(sizeof(double) * NWF * G);
+  double *Xs = nsp ? (double *)malloc(sizeof(double) * nsp * G) : NULL;
   double *Tnew = (double *)malloc(sizeof(double) * n);
   double *Pc = (double *)malloc(sizeof(double) * n); /* thermal P per cell */
 #pragma omp parallel for collapse(3) schedule(static) reduction(min : err)
@@ -638,6 +674,8 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
         if (rc < err) err = rc;
         Tnew[q] = t;
         Pc[q] = w[W_P];
+        for (int l = 0; l < nsp; ++l)
+          Xs[(size_t)l * G + gidx(&g, i, j, k)] = U[(5 + l) * n + q] / u[0];
         /* Delta W = W - W_hat (Sect. 2.8); the background has zero velocity
            and field, so only rho, P, gamma_e, gamma_c change */
         w[W_RHO] -= bg_cell(c, 0, k);
@@ -649,6 +687,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
       }
   if (err) {
     free(dW);
+    free(Xs);
     free(Tnew);
     free(Pc);
     return err;
@@ -682,6 +721,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
         if (i >= 0 && i < nx) continue;
         size_t d = gidx(&g, i, j, k), s = gidx(&g, wrap(i, nx), j, k);
         for (int f = 0; f < NWF; ++f) dW[f * G + d] = dW[f * G + s];
+        for (int l = 0; l < nsp; ++l) Xs[(size_t)l * G + d] = Xs[(size_t)l * G + s];
       }
   for (int k = 0; k < nz; ++k)
     for (int j = -NG; j < ny + NG; ++j) {
@@ -689,6 +729,7 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
       for (int i = -NG; i < nx + NG; ++i) {
         size_t d = gidx(&g, i, j, k), s = gidx(&g, i, wrap(j, ny), k);
         for (int f = 0; f < NWF; ++f) dW[f * G + d] = dW[f * G + s];
+        for (int l = 0; l < nsp; ++l) Xs[(size_t)l * G + d] = Xs[(size_t)l * G + s];
       }
     }
   for (int k = -NG; k < nz + NG; ++k) {
@@ -705,6 +746,8 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
           if (mir && (f == W_VZ || f == W_BZ)) v = -v;
           dW[f * G + d] = v;
         }
+        /* mass fractions are even across a wall */
+        for (int l = 0; l < nsp; ++l) Xs[(size_t)l * G + d] = Xs[(size_t)l * G + s];
       }
   }
 
@@ -722,11 +765,13 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
   /* step 4: fluxes on every face the update and the edge EMFs need.
      Face (i,j,k) of axis d is the lower face of cell (i,j,k) along d. */
   faceflux_t FF[3];
+  double *FX[3] = {NULL, NULL, NULL}; /* species fluxes [ns][G] per axis */
   for (int d = 0; d < 3; ++d) {
     for (int q = 0; q < NFLUX; ++q) {
       FF[d].F[q] = (double *)malloc(sizeof(double) * G);
     }
     FF[d].mass = (double *)malloc(sizeof(double) * G);
+    if (nsp) FX[d] = (double *)malloc(sizeof(double) * nsp * G);
   }
   for (int d = 0; d < 3; ++d) {
     int lo[3] = {-1, -1, -1}, hi[3] = {nx, ny, nz};
@@ -816,6 +861,37 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
           FF[d].mass[pR] = fx[F_MASS];
           /* eq. wb1: F <- F - F_hat */
           for (int q = 0; q < NFLUX; ++q) FF[d].F[q][pR] = fx[q] - Fh[q];
+          /* passive species (Sect. 2.9): face mass fractions reconstructed
+             like the primitives (van Leer, or the limited parabola in PPH
+             mode; van Leer in flattened cells), rescaled on each side so
+             they sum to one, and carried by the mass flux from the upwind
+             side (READING: the side of the contact that holds the face in
+             HLLC / HLLD, i.e. the sign of the mass flux; the same rule on
+             HLL faces), so the species fluxes add up to the mass flux */
+          if (nsp) {
+            double XL[64], XR[64], sL = 0.0, sR = 0.0;
+            for (int l = 0; l < nsp; ++l) {
+              const double *a = Xs + (size_t)l * G;
+              double unused;
+              if (pphL) {
+                orc_pph_limited(a[pL - st], a[pL], a[pR], &unused, &XL[l]);
+              } else {
+                double sl = orc_vanleer(a[pL] - a[pL - st], a[pR] - a[pL]);
+                XL[l] = a[pL] + 0.5 * sl;
+              }
+              if (pphR) {
+                orc_pph_limited(a[pL], a[pR], a[pR + st], &XR[l], &unused);
+              } else {
+                double sr = orc_vanleer(a[pR] - a[pL], a[pR + st] - a[pR]);
+                XR[l] = a[pR] - 0.5 * sr;
+              }
+              sL += XL[l];
+              sR += XR[l];
+            }
+            const double m = fx[F_MASS];
+            for (int l = 0; l < nsp; ++l)
+              FX[d][(size_t)l * G + pR] = m >= 0.0 ? m * (XL[l] / sL) : m * (XR[l] / sR);
+          }
         }
     if (ferr < err) err = ferr;
   }
@@ -952,6 +1028,15 @@ int orc_residual(const orc_cfg *c, const double *U, const double *Bx,
             s[4] += mx * fx + my * fy + mz * fz;
           }
           for (int f = 0; f < 5; ++f) RU[f * n + q] = r[f] - s[f];
+          /* species: divergence of their fluxes (no sources) */
+          for (int l = 0; l < nsp; ++l) {
+            double rx = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              const double *Fl = FX[d] + (size_t)l * G;
+              rx += (Fl[p + off[d]] - Fl[p]) / dxs[d];
+            }
+            RU[(5 + l) * n + q] = rx;
+          }
         }
     /* faces: R_f = (1/A_f) sum_d l_d E_d = (curl E)_n (eq. induction) */
 #pragma omp parallel for collapse(3) schedule(static)
@@ -986,8 +1071,10 @@ done:
   for (int d = 0; d < 3; ++d) {
     for (int q = 0; q < NFLUX; ++q) free(FF[d].F[q]);
     free(FF[d].mass);
+    free(FX[d]);
   }
   free(dW);
+  free(Xs);
   return err;
 }
 
@@ -1010,15 +1097,16 @@ int orc_step(const orc_cfg *c, double *U, double *Bx, double *By, double *Bz,
   grid_init(c, &g);
   const size_t n = (size_t)g.nx * g.ny * g.nz;
   const size_t nf = (size_t)g.nx * g.ny * g.nzf;
-  /* one buffer holding U, Bx, By, Bz back to back */
-  const size_t tot = 5 * n + 2 * n + nf;
+  /* one buffer holding U (with the species), Bx, By, Bz back to back */
+  const size_t nu = (size_t)(5 + c->nspecies) * n;
+  const size_t tot = nu + 2 * n + nf;
   double *S0 = (double *)malloc(sizeof(double) * tot);
   double *S1 = (double *)malloc(sizeof(double) * tot);
   double *R = (double *)malloc(sizeof(double) * tot);
-  memcpy(S0, U, sizeof(double) * 5 * n);
-  memcpy(S0 + 5 * n, Bx, sizeof(double) * n);
-  memcpy(S0 + 6 * n, By, sizeof(double) * n);
-  memcpy(S0 + 7 * n, Bz, sizeof(double) * nf);
+  memcpy(S0, U, sizeof(double) * nu);
+  memcpy(S0 + nu, Bx, sizeof(double) * n);
+  memcpy(S0 + nu + n, By, sizeof(double) * n);
+  memcpy(S0 + nu + 2 * n, Bz, sizeof(double) * nf);
   /* stage coefficients (a, b, c): U_new = a U^n + b U^(s) - c dt R(U^(s)) */
   static const double rk2[2][3] = {{0.0, 1.0, 1.0}, {0.5, 0.5, 0.5}};
   static const double rk3[3][3] = {
@@ -1030,17 +1118,17 @@ int orc_step(const orc_cfg *c, double *U, double *Bx, double *By, double *Bz,
   int err = ORC_OK;
   const double *Us = S0;
   for (int s = 0; s < ns; ++s) {
-    err = orc_residual(c, Us, Us + 5 * n, Us + 6 * n, Us + 7 * n, Tw, Tw, R,
-                       R + 5 * n, R + 6 * n, R + 7 * n);
+    err = orc_residual(c, Us, Us + nu, Us + nu + n, Us + nu + 2 * n, Tw, Tw, R, R + nu,
+                       R + nu + n, R + nu + 2 * n);
     if (err) break;
     combine(tot, co[s][0], S0, co[s][1], Us, co[s][2] * dt, R, S1);
     Us = S1;
   }
   if (!err) {
-    memcpy(U, S1, sizeof(double) * 5 * n);
-    memcpy(Bx, S1 + 5 * n, sizeof(double) * n);
-    memcpy(By, S1 + 6 * n, sizeof(double) * n);
-    memcpy(Bz, S1 + 7 * n, sizeof(double) * nf);
+    memcpy(U, S1, sizeof(double) * nu);
+    memcpy(Bx, S1 + nu, sizeof(double) * n);
+    memcpy(By, S1 + nu + n, sizeof(double) * n);
+    memcpy(Bz, S1 + nu + 2 * n, sizeof(double) * nf);
   }
   free(S0);
   free(S1);

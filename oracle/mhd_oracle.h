@@ -8,7 +8,8 @@
  * HIP path.
  *
  * Grid and storage (all arrays FP64, x fastest, interior cells only):
- *   U   [5][nz][ny][nx]   rho, m_x, m_y, m_z, E  (E includes |B_cc|^2/2)
+ *   U   [5+ns][nz][ny][nx] rho, m_x, m_y, m_z, E (E includes |B_cc|^2/2),
+ *                         then rho X_l of the ns passive species (Sect. 2.9)
  *   Bx  [nz][ny][nx]      face i holds B_x at x_{i-1/2}      (x periodic)
  *   By  [nz][ny][nx]      face j holds B_y at y_{j-1/2}      (y periodic)
  *   Bz  [nzf][ny][nx]     face k holds B_z at z_{k-1/2}; nzf = nz when z is
@@ -61,6 +62,7 @@ typedef struct {
   int recon;             /* ORC_RECON_*                                     */
   int flatten;           /* 1: shock flattening (Sect. 2.7), 0: off         */
   double eps_sf;         /* threshold epsilon_SF of the shock detector      */
+  int nspecies;          /* passive species ns carried as rho X_l in U      */
   const double *bg_cc;   /* [4][nz]  background rho, P, gamma_e, gamma_c at
                             cell centres, or NULL for a zero background     */
   const double *bg_fz;   /* [4][nzf] the same at z faces (NULL with bg_cc)  */
@@ -85,6 +87,12 @@ double orc_vanleer(double a, double b);
 /* PPH face values of a cell from its own and its neighbours' averages
    (Sect. 2.5): lo = value at the lower face, hi = at the upper face. */
 void orc_pph(double wm, double wc, double wp, double *lo, double *hi);
+
+/* Limited parabola of the mass fractions in PPH mode (Sect. 2.5): the
+   face values of the three-cell parabola of orc_pph bounded by the averages
+   beside each face, then made monotone inside the cell with the constraints
+   of Colella & Woodward (1984). */
+void orc_pph_limited(double wm, double wc, double wp, double *lo, double *hi);
 
 /* HLLD / LHLLD interface flux (Sect. 2.6, eq. flux-hlld) in the face frame.
    W = {rho, v_n, v_t1, v_t2, P, B_t1, B_t2, gamma_e, gamma_c};

@@ -33,7 +33,7 @@ class _Cfg(C.Structure):
         ("rk_order", C.c_int), ("newton_tol", C.c_double),
         ("newton_maxit", C.c_int), ("mach_cut", C.c_double),
         ("xi_mode", C.c_int), ("recon", C.c_int),
-        ("flatten", C.c_int), ("eps_sf", C.c_double),
+        ("flatten", C.c_int), ("eps_sf", C.c_double), ("nspecies", C.c_int),
         ("bg_cc", _DP), ("bg_fz", _DP), ("heat", _DP), ("force", _DP),
     ]
 
@@ -73,6 +73,8 @@ def lib():
         L.orc_vanleer.argtypes = [C.c_double, C.c_double]
         L.orc_pph.argtypes = [C.c_double, C.c_double, C.c_double, _DP, _DP]
         L.orc_pph.restype = None
+        L.orc_pph_limited.argtypes = [C.c_double, C.c_double, C.c_double, _DP, _DP]
+        L.orc_pph_limited.restype = None
         OP = C.POINTER(_Opacity)
         L.orc_diffusion_rhs.argtypes = [C.POINTER(_Cfg), OP, _DP, _DP, _DP]
         L.orc_parabolic_dt.argtypes = [C.POINTER(_Cfg), OP, _DP, _DP, _DP]
@@ -105,7 +107,7 @@ def _check(rc, what):
 DEFAULTS = dict(
     bcz=BC_PERIODIC, eos=EOS_IDEAL, gamma=5.0 / 3.0, mu=0.6, rgas=0.0, arad=0.0,
     gz=0.0, rk_order=2, newton_tol=1e-11, newton_maxit=50, mach_cut=0.6,
-    xi_mode=XI_LINEAR, recon=RECON_VANLEER, flatten=0, eps_sf=0.2,
+    xi_mode=XI_LINEAR, recon=RECON_VANLEER, flatten=0, eps_sf=0.2, nspecies=0,
 )
 
 
@@ -131,7 +133,8 @@ class Oracle:
             int(p["bcz"]), int(p["eos"]), float(p["gamma"]), float(p["mu"]),
             float(p["rgas"]), float(p["arad"]), float(p["gz"]), int(p["rk_order"]),
             float(p["newton_tol"]), int(p["newton_maxit"]), float(p["mach_cut"]),
-            int(p["xi_mode"]), int(p["recon"]), int(p["flatten"]), float(p["eps_sf"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
+            int(p["xi_mode"]), int(p["recon"]), int(p["flatten"]), float(p["eps_sf"]),
+            int(p["nspecies"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
         )
 
     # -- state helpers -------------------------------------------------
@@ -139,7 +142,7 @@ class Oracle:
         U = st["U"]
         for k in ("U", "Bx", "By", "Bz"):
             assert st[k].dtype == np.float64 and st[k].flags["C_CONTIGUOUS"], k
-        assert U.shape == (5,) + self.shape
+        assert U.shape == (5 + int(self.p["nspecies"]),) + self.shape
         T = st.get("T")
         if self.p["eos"] == EOS_GASRAD:
             assert T is not None and T.shape == self.shape
@@ -271,6 +274,13 @@ def pph(wm: float, wc: float, wp: float):
     """(lower, upper) face values of the PPH parabola of a cell."""
     lo, hi = C.c_double(), C.c_double()
     lib().orc_pph(float(wm), float(wc), float(wp), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def pph_limited(wm: float, wc: float, wp: float):
+    """(lower, upper) face values of the limited parabola of a mass fraction."""
+    lo, hi = C.c_double(), C.c_double()
+    lib().orc_pph_limited(float(wm), float(wc), float(wp), C.byref(lo), C.byref(hi))
     return lo.value, hi.value
 
 

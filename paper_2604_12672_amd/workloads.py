@@ -510,6 +510,30 @@ def config(idx: int, n: int | None = None):
     raise ValueError(idx)
 
 
+def add_species(w, ns, seed=9, kmax=2, contrast=0.9):
+    """The workload with ns passive species (Sect. 2.9): smooth positive mass
+    fractions X_l = f_l / sum_m f_m, f_l = 1 + contrast x (a few random low
+    Fourier modes, scaled into [-1, 1]), so they sum to one; U gains the rows
+    rho X_l after its five fluid rows."""
+    p = dict(w.params, nspecies=int(ns))
+    xc, yc, zc, *_ = _centres(p)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    rng = np.random.default_rng(seed)
+    f = np.empty((ns,) + X.shape)
+    for l in range(ns):
+        g = np.zeros_like(X)
+        for _ in range(3):
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            g += rng.normal() * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z)
+                                       + rng.uniform(0, 2 * np.pi))
+        g /= max(np.abs(g).max(), 1e-300)
+        f[l] = 1.0 + contrast * g
+    Xl = f / f.sum(axis=0)
+    U = np.ascontiguousarray(np.concatenate([w.U[:5], w.U[0][None] * Xl], axis=0))
+    return Workload(w.name + f"+{ns}sp", p, U, w.Bx, w.By, w.Bz, T=w.T, bg_cc=w.bg_cc,
+                    bg_fz=w.bg_fz, heat=w.heat, force=w.force, cfl=w.cfl, steps=w.steps)
+
+
 def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2, eos=EOS_IDEAL,
                blast=None):
     """Smooth random state on [0,1]^3 (parity tests on ragged grids): rho and
