@@ -85,6 +85,8 @@ extern "C" {
 #define MHD_HOST 0
 #define MHD_DEVICE 1
 
+#define MHD_MAX_SPECIES 16
+
 typedef struct mhd_ctx mhd_ctx; /* opaque */
 
 typedef struct {
@@ -106,6 +108,7 @@ typedef struct {
   int32_t recon;          /* MHD_RECON_*                                       */
   int32_t flatten;        /* 1: shock flattening (Sect. 2.7), 0: off           */
   double eps_sf;          /* detector threshold epsilon_SF (paper: 0.2), > 0   */
+  int32_t nspecies;       /* passive species 0 .. MHD_MAX_SPECIES (Sect. 2.9)  */
 } mhd_grid_desc;
 
 typedef struct {
@@ -196,6 +199,18 @@ int mhd_advance(mhd_ctx *ctx, double cfl, int32_t nsteps);
    the guess kept for the next step is not changed. */
 int mhd_get_state(mhd_ctx *ctx, double *U, double *Bx, double *By, double *Bz,
                   double *T, int32_t where);
+
+/* Passive species (Sect. 2.9): rhoX [ns][nz][ny][nx], the partial
+   densities rho X_l (FP64, `where` as for mhd_set_state), for contexts
+   with nspecies = ns > 0 (else MHD_ERR_STATE).  Each RK stage advects them
+   with the stage's face mass fluxes: the mass fractions are reconstructed
+   like the primitives (van Leer; in PPH mode a parabola limited to stay
+   monotone; van Leer in flattened cells), rescaled on each side of a face
+   to sum to one, and taken from the upwind side of the mass flux, so the
+   species masses add up to the density.  mhd_set_species must follow
+   mhd_set_state before the first step; mhd_get_species synchronises. */
+int mhd_set_species(mhd_ctx *ctx, const double *rhoX, int32_t where);
+int mhd_get_species(mhd_ctx *ctx, double *rhoX, int32_t where);
 
 /* Shock-flattening flags (Sect. 2.7) of the current state, one byte per
    cell [nz][ny][nx] (1 = flattened: van Leer reconstruction and HLL on its

@@ -109,6 +109,10 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "recon must be MHD_RECON_VANLEER or MHD_RECON_PPH";
     return MHD_ERR_ARG;
   }
+  if (d->nspecies < 0 || d->nspecies > MHD_MAX_SPECIES) {
+    msg = "nspecies must be 0 .. MHD_MAX_SPECIES";
+    return MHD_ERR_ARG;
+  }
   if (d->flatten != 0 && d->flatten != 1) {
     msg = "flatten must be 0 or 1";
     return MHD_ERR_ARG;
@@ -295,6 +299,14 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   if ((e = hipMalloc(&c.flags, sizeof(int))) != hipSuccess) return cleanup(e, "hipMalloc flags");
   if ((e = hipMalloc(&c.nstats, sizeof(unsigned long long) * 3)) != hipSuccess)
     return cleanup(e, "hipMalloc stats");
+  if (desc->nspecies > 0) {
+    for (int s = 0; s < 3; ++s)
+      if ((e = hipMalloc(&c.X[s], sizeof(double) * desc->nspecies * c.ncell)) != hipSuccess)
+        return cleanup(e, "hipMalloc species");
+    for (int a = 0; a < 3; ++a)
+      if ((e = hipMalloc(&c.mf[a], sizeof(double) * (a == 2 ? c.nfz : c.ncell))) != hipSuccess)
+        return cleanup(e, "hipMalloc mass fluxes");
+  }
   if (desc->flatten) {
     if ((e = hipMalloc(&c.shock_p, sizeof(double) * c.ncell)) != hipSuccess)
       return cleanup(e, "hipMalloc shock pressure");
@@ -332,6 +344,10 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.nstats);
   (void)hipFree(c.mlp);
   (void)hipFree(c.shock_p);
+  for (int s = 0; s < 3; ++s) {
+    (void)hipFree(c.X[s]);
+    (void)hipFree(c.mf[s]);
+  }
   (void)hipFree(c.shock_f);
   mhd::DiffBufs &d = c.diff;
   (void)hipFree(d.e0);
@@ -413,6 +429,30 @@ int mhd_set_state(mhd_ctx *h, const double *U, const double *Bx, const double *B
                                              c.T[c.tcur]));
   }
   c.have_state = true;
+  c.have_species = false;
+  return latched(h);
+}
+
+int mhd_set_species(mhd_ctx *h, const double *rhoX, int32_t where) {
+  if (!h || !rhoX) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (c.d.nspecies <= 0) return fail(h, MHD_ERR_STATE, "context created without species");
+  if (!c.have_state) return fail(h, MHD_ERR_STATE, "mhd_set_species before mhd_set_state");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  HIPCHK(h, hipMemcpyAsync(c.X[c.cur], rhoX, sizeof(double) * c.d.nspecies * c.ncell,
+                           kind_in(where), c.stream));
+  c.have_species = true;
+  return latched(h);
+}
+
+int mhd_get_species(mhd_ctx *h, double *rhoX, int32_t where) {
+  if (!h || !rhoX) return MHD_ERR_ARG;
+  mhd::Ctx &c = h->c;
+  if (c.d.nspecies <= 0) return fail(h, MHD_ERR_STATE, "context created without species");
+  if (!c.have_species) return fail(h, MHD_ERR_STATE, "mhd_get_species before mhd_set_species");
+  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  HIPCHK(h, hipMemcpyAsync(rhoX, c.X[c.cur], sizeof(double) * c.d.nspecies * c.ncell,
+                           kind_out(where), c.stream));
   return latched(h);
 }
 
@@ -420,6 +460,8 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
   mhd::Ctx &c = h->c;
   if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
+  if (c.d.nspecies > 0 && !c.have_species)
+    return fail(h, MHD_ERR_STATE, "species context stepped before mhd_set_species");
   const int ns = c.d.rk_order == 3 ? 3 : 2;
   const double(*co)[3] = c.d.rk_order == 3 ? kRK3 : kRK2;
   const int n = c.cur;
@@ -469,7 +511,15 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.dt_dev = dt_dev;
     p.flags = c.flags;
     p.newton_stats = c.nstats;
+    if (c.d.nspecies > 0) {
+      p.mfx = c.mf[0];
+      p.mfy = c.mf[1];
+      p.mfz = c.mf[2];
+    }
     HIPCHK(h, mhd::launch_stage(c, p, co[s][0], co[s][1], co[s][2], dt_host));
+    if (c.d.nspecies > 0)
+      HIPCHK(h, mhd::launch_species(c, c.U[in], c.X[in], c.X[n], c.X[o], co[s][0], co[s][1],
+                                    co[s][2], dt_host, dt_dev, p.flat));
     if (prev_t) c.tcur = 1 - c.tcur;
     in = o;
   }

@@ -53,6 +53,8 @@ struct StagePtrs {
   const double *dt_dev;                // device dt (nullable: use dt_host)
   int newton_cap;                      // Newton steps before the bracketed solve
   const uint8_t *flat = nullptr;       // shock-flattening flags [n] (nullable)
+  double *mfx = nullptr, *mfy = nullptr, *mfz = nullptr;  // face mass fluxes out
+                                       // (lower faces; nullable: no species)
   int *flags;                          // latched error flags
   unsigned long long *newton_stats;    // [3]: iterations, max, fallbacks
 };
@@ -105,6 +107,11 @@ struct Ctx {
   // (one byte per cell), allocated when enabled
   double *shock_p = nullptr;
   uint8_t *shock_f = nullptr;
+  // passive species: rho X_l [ns][n] per state buffer (rotated with U) and
+  // the face mass fluxes of the current stage (x, y: [n]; z: [nfz])
+  double *X[3] = {nullptr, nullptr, nullptr};
+  double *mf[3] = {nullptr, nullptr, nullptr};
+  bool have_species = false;
   int zseg = 32;
   std::string err;
 };
@@ -146,6 +153,11 @@ hipError_t launch_shock_pressure(const Ctx &c, const double *U, const double *Bx
                                  const double *By, const double *Bz, const double *Tg,
                                  int newton_cap);
 hipError_t launch_shock_flags(const Ctx &c);
+// species update of one RK stage (mhd_species.hip): Xo = a X0 + b Xs -
+// c dt div(F_mass X_up); rho is the stage input density
+hipError_t launch_species(const Ctx &c, const double *rho, const double *Xs, const double *X0,
+                          double *Xo, double a, double b, double cc, double dt_host,
+                          const double *dt_dev, const uint8_t *flat);
 hipError_t launch_eos_solve(const Ctx &c, const double *rho, const double *e,
                             const double *tguess, long long n, double *T, double *T0,
                             bool stats);

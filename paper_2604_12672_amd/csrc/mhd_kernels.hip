@@ -469,6 +469,11 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           R fz[7];
           face_flux<R, GR>((fk | fc) != 0, topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut,
                            imcut, fz);
+          // mass flux for the species: the lower face of cell k+1 (and the
+          // top wall), written once, by the block that owns the cell
+          const int f = k + 1;
+          if (p.mfz && owner && ((f >= z0 && f < z1) || (ph.reflect && f == ph.nz)))
+            p.mfz[(size_t)f * plane + colq] = (double)fz[0];
           to_cons<R>(2, fz, fzc);
           zf_ey = -fz[5];  // z-face E_y = -F_z[B_x]
           zf_ex = fz[6];   // z-face E_x = +F_z[B_y]
@@ -526,6 +531,13 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       to_cons<R>(1, fy, fyc);
 #pragma unroll
       for (int f = 0; f < 5; ++f) sYF[f][tid] = fyc[f];
+      // mass fluxes for the species: the lower x and y faces of the owned
+      // cells of plane k+1
+      if (p.mfx && owner && k + 1 >= z0 && k + 1 < z1) {
+        const size_t qf = (size_t)(k + 1) * plane + colq;
+        p.mfx[qf] = (double)fx[0];
+        p.mfy[qf] = (double)fy[0];
+      }
       sXE[0][tid] = -fx[5];  // x-face E_z = -F_x[B_y]
       sXE[1][tid] = fx[0];
       sZE[0][tid] = zf_ex;

@@ -44,7 +44,7 @@ class GridDesc(C.Structure):
         ("rk_order", C.c_int32), ("precision", C.c_int32), ("eos_guess", C.c_int32),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("mach_cut", C.c_double),
         ("xi_mode", C.c_int32), ("recon", C.c_int32), ("flatten", C.c_int32),
-        ("eps_sf", C.c_double),
+        ("eps_sf", C.c_double), ("nspecies", C.c_int32),
     ]
 
 
@@ -59,7 +59,7 @@ class Diag(C.Structure):
 EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eos_mlp",
            "mhd_eos_solve", "mhd_set_state", "mhd_compute_dt", "mhd_step", "mhd_advance",
            "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
-           "mhd_shock_flags",
+           "mhd_shock_flags", "mhd_set_species", "mhd_get_species",
            "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse"]
 
 _lib = None
@@ -91,6 +91,8 @@ def load():
     L.mhd_get_state.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
     L.mhd_sync.argtypes = [vp]
     L.mhd_shock_flags.argtypes = [vp, vp, C.c_int32]
+    L.mhd_set_species.argtypes = [vp, vp, C.c_int32]
+    L.mhd_get_species.argtypes = [vp, vp, C.c_int32]
     L.mhd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
     L.mhd_last_error.argtypes = [vp]
     L.mhd_last_error.restype = C.c_char_p
@@ -131,6 +133,7 @@ def make_desc(params: dict, precision=PREC_FP64, eos_guess=GUESS_PREV_T) -> Grid
     d.recon = int(p.get("recon", RECON_VANLEER))
     d.flatten = int(p.get("flatten", 0))
     d.eps_sf = float(p.get("eps_sf", 0.2))
+    d.nspecies = int(p.get("nspecies", 0))
     return d
 
 
@@ -271,7 +274,27 @@ class Grid:
             self.set_background(w.bg_cc, w.bg_fz)
         if w.heat is not None or w.force is not None:
             self.set_sources(w.heat, w.force)
-        self.set_state(w.U, w.Bx, w.By, w.Bz, w.T if guess else None)
+        ns = int(w.params.get("nspecies", 0))
+        self.set_state(np.ascontiguousarray(w.U[:5]) if ns else w.U, w.Bx, w.By, w.Bz,
+                       w.T if guess else None)
+        if ns:
+            self.set_species(w.U[5:])
+
+    def set_species(self, rhoX):
+        """Partial densities rho X_l [ns][nz][ny][nx] (numpy or CUDA tensor)."""
+        w = _where(rhoX)
+        if not _is_torch(rhoX):
+            rhoX = np.ascontiguousarray(rhoX, dtype=np.float64)
+        assert tuple(rhoX.shape) == (self.desc.nspecies,) + self.shape
+        self._check(self._L.mhd_set_species(self._h, _ptr(rhoX, w), w))
+
+    def get_species(self, out=None):
+        if out is None:
+            out = np.empty((self.desc.nspecies,) + self.shape)
+        w = _where(out)
+        assert tuple(out.shape) == (self.desc.nspecies,) + self.shape
+        self._check(self._L.mhd_get_species(self._h, _ptr(out, w), w))
+        return out
 
     # -- stepping --------------------------------------------------------
     def step(self, dt):

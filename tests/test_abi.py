@@ -54,6 +54,7 @@ int main(void) {
   O(mhd_grid_desc, gamma); O(mhd_grid_desc, grav); O(mhd_grid_desc, rk_order);
   O(mhd_grid_desc, newton_tol); O(mhd_grid_desc, mach_cut); O(mhd_grid_desc, xi_mode);
   O(mhd_grid_desc, recon); O(mhd_grid_desc, flatten); O(mhd_grid_desc, eps_sf);
+  O(mhd_grid_desc, nspecies);
   O(mhd_diag, total); O(mhd_diag, newton_iters); O(mhd_diag, error_flags);
   return 0;
 }
@@ -84,6 +85,7 @@ def _desc(**kw):
     dict(eos=1, rgas=0.0), dict(xi_mode=9), dict(mach_cut=0.0),
     dict(nx=2048, ny=2048, nz=1024), dict(recon=4), dict(flatten=2),
     dict(flatten=1, eps_sf=0.0), dict(flatten=1, eps_sf=float("nan")),
+    dict(nspecies=-1), dict(nspecies=17),
 ])
 def test_descriptor_validation(lib, bad):
     d = _desc(**bad)
