@@ -11,9 +11,8 @@
 // averages beside each face and made monotone after Colella & Woodward;
 // van Leer in flattened cells), rescales them to sum to one, and
 // accumulates flux x fraction.  The update is the stage's combination
-// a X^n + b X^(s) - c dt div.  One cell per thread over XCD-contiguous
-// chunks; each face is evaluated by both of its cells, the stencils come
-// from the caches.
+// a X^n + b X^(s) - c dt div.  One cell per thread; each face is evaluated
+// by both of its cells, the stencils come from the caches.
 #include <hip/hip_runtime.h>
 
 #include "mhd_device.h"
@@ -71,6 +70,12 @@ __device__ __forceinline__ int axis_cell(int a, int n, bool wall) {
   return a;
 }
 
+// One block per 16 x 16 tile of one plane.  Each face's
+// fractions are used as soon as they are reconstructed, so the registers
+// hold the accumulators and one face's fractions (NS each).
+constexpr int SP_T = 16;  // tile edge (256 threads)
+
+template <int NS>
 __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, int ns, double ca,
                                                       double cb, double cc, double dt_host) {
   const size_t plane = (size_t)ph.nx * ph.ny;
@@ -78,70 +83,77 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
   const double dt = p.dt_dev ? *p.dt_dev : dt_host;
   const double cdt = cc * dt;
   const bool pph = ph.recon == MHD_RECON_PPH;
-  const double idxs[3] = {ph.idx, ph.idy, ph.idz};
+  // logical order: x tiles fastest, then planes, then rows of tiles, so the
+  // blocks in flight on one XCD cover whole rows of tiles over a few planes
+  // (x halos and z stencils come from L2)
+  const int ntx = (ph.nx + SP_T - 1) / SP_T;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int btx = lb % ntx, rest = lb / ntx;
+  const int kk = rest % ph.nz, bty = rest / ph.nz;
+  const int ii = btx * SP_T + (int)(threadIdx.x % SP_T);
+  const int jj = bty * SP_T + (int)(threadIdx.x / SP_T);
+  if (ii >= ph.nx || jj >= ph.ny) return;
+  const size_t q = (size_t)kk * plane + (size_t)jj * ph.nx + ii;
+  const int ijk[3] = {ii, jj, kk};
   const int lens[3] = {ph.nx, ph.ny, ph.nz};
-  size_t c0, c1;
-  block_cells(n, c0, c1);
-  for (size_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) {
-    int ijk[3];
-    cell_ijk(ph, q, ijk[0], ijk[1], ijk[2]);
-    double r[MHD_MAX_SPECIES];
+  const double idxs[3] = {ph.idx, ph.idy, ph.idz};
+  double r[NS];
 #pragma unroll
-    for (int l = 0; l < MHD_MAX_SPECIES; ++l) r[l] = 0.0;
-    for (int axis = 0; axis < 3; ++axis) {
-      // an axis of one cell carries the same face below and above the cell
-      // with the same upwind values: no divergence
-      if (!ph.dims_active[axis]) continue;
-      const int len = lens[axis];
-      const bool wall = axis == 2 && ph.reflect;
-      const size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)ph.nx : plane);
-      const int a0 = ijk[axis];
-      const size_t base = q - (size_t)a0 * stride;  // the cell at index 0 on this line
-      double fl[2];                   // mass flux / sum of fractions, per face
-      double ff[2][MHD_MAX_SPECIES];  // upwind face fractions, per face
-      for (int side = 0; side < 2; ++side) {
-        // the face: lower (side 0) at a0 - 1/2, upper (side 1) at a0 + 1/2
-        double F;
-        if (axis == 0)
-          F = p.mfx[base + (size_t)wrapi(a0 + side, len)];
-        else if (axis == 1)
-          F = p.mfy[base + (size_t)wrapi(a0 + side, len) * stride];
-        else
-          F = p.mfz[base + (size_t)(wall ? a0 + side : wrapi(a0 + side, len)) * stride];
-        // upwind cell and which of its faces this is
-        const int u = F >= 0.0 ? a0 + side - 1 : a0 + side;
-        const bool upper = F >= 0.0;
-        const size_t qm = base + (size_t)axis_cell(u - 1, len, wall) * stride;
-        const size_t qu = base + (size_t)axis_cell(u, len, wall) * stride;
-        const size_t qp = base + (size_t)axis_cell(u + 1, len, wall) * stride;
-        const bool par = pph && !(p.flat && p.flat[qu]);
-        const double im = rcp<double>(p.rho[qm]), iu = rcp<double>(p.rho[qu]),
-                     ip = rcp<double>(p.rho[qp]);
-        double sum = 0.0;
+  for (int l = 0; l < NS; ++l) r[l] = 0.0;
+  // every loop below is unrolled, so the per-species arrays stay in
+  // registers (an index the compiler cannot resolve would put them in
+  // scratch memory)
 #pragma unroll
-        for (int l = 0; l < MHD_MAX_SPECIES; ++l) {
-          if (l < ns) {
-            const double* X = p.Xs + (size_t)l * n;
-            const double v = fraction_face(X[qm] * im, X[qu] * iu, X[qp] * ip, upper, par);
-            ff[side][l] = v;
-            sum += v;
-          }
+  for (int axis = 0; axis < 3; ++axis) {
+    // an axis of one cell carries the same face below and above the cell
+    // with the same upwind values: no divergence
+    if (!ph.dims_active[axis]) continue;
+    const int len = lens[axis];
+    const bool wall = axis == 2 && ph.reflect;
+    const size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)ph.nx : plane);
+    const int a0 = ijk[axis];
+    const size_t base = q - (size_t)a0 * stride;  // the cell at index 0 on this line
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      // the face: lower (side 0) at a0 - 1/2, upper (side 1) at a0 + 1/2
+      const double *mf = axis == 0 ? p.mfx : (axis == 1 ? p.mfy : p.mfz);
+      const int fa = wall ? a0 + side : wrapi(a0 + side, len);
+      const double F = mf[base + (size_t)fa * stride];
+      // upwind cell and which of its faces this is
+      const int u = F >= 0.0 ? a0 + side - 1 : a0 + side;
+      const bool upper = F >= 0.0;
+      const size_t qm = base + (size_t)axis_cell(u - 1, len, wall) * stride;
+      const size_t qu = base + (size_t)axis_cell(u, len, wall) * stride;
+      const size_t qp = base + (size_t)axis_cell(u + 1, len, wall) * stride;
+      const bool par = pph && !(p.flat && p.flat[qu]);
+      const double im = rcp<double>(p.rho[qm]), iu = rcp<double>(p.rho[qu]),
+                   ip = rcp<double>(p.rho[qp]);
+      double v[NS];
+      double sum = 0.0;
+#pragma unroll
+      for (int l = 0; l < NS; ++l) {
+        v[l] = 0.0;
+        if (l < ns) {
+          const double *X = p.Xs + (size_t)l * n;
+          v[l] = fraction_face(X[qm] * im, X[qu] * iu, X[qp] * ip, upper, par);
+          sum += v[l];
         }
-        fl[side] = F * rcp<double>(sum);
       }
-      const double id = idxs[axis];
+      // flux of species l: F v_l / sum, entering the divergence with the
+      // face's sign
+      const double g = (side ? F : -F) * rcp<double>(sum) * idxs[axis];
 #pragma unroll
-      for (int l = 0; l < MHD_MAX_SPECIES; ++l)
-        if (l < ns) r[l] += (fl[1] * ff[1][l] - fl[0] * ff[0][l]) * id;
+      for (int l = 0; l < NS; ++l)
+        if (l < ns) r[l] += g * v[l];
     }
+  }
 #pragma unroll
-    for (int l = 0; l < MHD_MAX_SPECIES; ++l) {
-      if (l < ns) {
-        const size_t o = (size_t)l * n + q;
-        double v = cb * p.Xs[o] - cdt * r[l];
-        if (ca != 0.0) v += ca * p.X0[o];
-        p.Xo[o] = v;
-      }
+  for (int l = 0; l < NS; ++l) {
+    if (l < ns) {
+      const size_t o = (size_t)l * n + q;
+      double val = cb * p.Xs[o] - cdt * r[l];
+      if (ca != 0.0) val += ca * p.X0[o];
+      p.Xo[o] = val;
     }
   }
 }
@@ -159,10 +171,21 @@ hipError_t launch_species(const Ctx &c, const double *rho, const double *Xs, con
   p.mfz = c.mf[2];
   p.flat = flat;
   p.dt_dev = dt_dev;
-  long long nb = (long long)((c.ncell + 255) / 256);
-  nb = nb < 65536 ? nb : 65536;
-  hipLaunchKernelGGL(species_kernel, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph, p,
-                     c.d.nspecies, a, b, cc, dt_host);
+  const int ns = c.d.nspecies;
+  const dim3 grid(((c.ph.nx + SP_T - 1) / SP_T) * ((c.ph.ny + SP_T - 1) / SP_T) * c.ph.nz);
+  // register arrays sized for the species count (a few variants)
+  if (ns <= 4)
+    hipLaunchKernelGGL(species_kernel<4>, grid, dim3(256), 0, c.stream, c.ph, p, ns, a, b, cc,
+                       dt_host);
+  else if (ns <= 8)
+    hipLaunchKernelGGL(species_kernel<8>, grid, dim3(256), 0, c.stream, c.ph, p, ns, a, b, cc,
+                       dt_host);
+  else if (ns <= 12)
+    hipLaunchKernelGGL(species_kernel<12>, grid, dim3(256), 0, c.stream, c.ph, p, ns, a, b, cc,
+                       dt_host);
+  else
+    hipLaunchKernelGGL(species_kernel<16>, grid, dim3(256), 0, c.stream, c.ph, p, ns, a, b, cc,
+                       dt_host);
   return hipGetLastError();
 }
 
