@@ -338,9 +338,53 @@ def cpu_baseline(n, target_s=12.0):
         if time.perf_counter() - t0 > target_s:
             break
     el = time.perf_counter() - t0
-    return {"value": round(w.ncells * steps / el, 1), "unit": "zone-updates/s",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"stratified box {n}^3, {steps} SSP-RK2 steps incl. CFL, {el:.1f} s"}
+    out = {"value": round(w.ncells * steps / el, 1), "unit": "zone-updates/s",
+           "cores": orc.num_threads(), "kind": "oracle",
+           "sample": f"stratified box {n}^3, {steps} SSP-RK2 steps incl. CFL, {el:.1f} s"}
+    # one core, for scale against per-core CPU figures (a smaller sample)
+    threads = orc.num_threads()
+    orc.set_num_threads(1)
+    try:
+        w1 = wl.stratified_box(48)
+        o1 = orc.Oracle(w1.params, **w1.extras())
+        s1 = w1.state()
+        o1.step(s1, o1.compute_dt(s1, w1.cfl))
+        k1 = 0
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < target_s / 3:
+            o1.step(s1, o1.compute_dt(s1, w1.cfl))
+            k1 += 1
+        e1 = time.perf_counter() - t1
+    finally:
+        orc.set_num_threads(threads)
+    out["single_core"] = {"value": round(w1.ncells * k1 / e1, 1), "unit": "zone-updates/s",
+                          "us_per_cell_step": round(e1 / (w1.ncells * k1) * 1e6, 3),
+                          "sample": f"stratified box 48^3, {k1} steps, {e1:.1f} s"}
+    return out
+
+
+def stream_ceiling():
+    """Measured copy bandwidth of the device: a 2 GiB torch copy (2 GiB read,
+    2 GiB written), best of five, HIP events."""
+    import torch
+    a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 2 ** 31 / (best * 1e-3) / 1e9
 
 
 def host_transfer(mhd, w):
@@ -545,6 +589,10 @@ def main():
         "roofline": roofline(w, r["stage_ms"], main_name),
         "divb_max": r["diag"]["divb_max"],
     }
+    ceil = stream_ceiling()
+    out["roofline"]["measured_copy_GBs"] = round(ceil, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(out["roofline"]["achieved"] / ceil, 4)
+    log(f"bench: device copy ceiling {ceil:.0f} GB/s")
     t_in, t_out = host_transfer(mhd, w)
     out["pcie_inclusive"] = {
         "set_state_host_s": round(t_in, 4), "get_state_host_s": round(t_out, 4),

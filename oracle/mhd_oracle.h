@@ -141,8 +141,10 @@ int orc_primitives(const orc_cfg *c, const double *U, const double *Bx,
                    const double *By, const double *Bz, const double *Tguess,
                    double *Tout, double *out);
 
-/* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
+/* Number of OpenMP threads the oracle runs with (1 without OpenMP), and a
+   setter for the following calls (n > 0). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* ------------------------------------------------------------------ */
 /* Thermal diffusion and RKL2 super-time-stepping (Sect. 2.10),        */

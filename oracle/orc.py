@@ -85,6 +85,8 @@ def lib():
                                   C.c_int, C.c_int]
         L.orc_vanleer.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
     return _lib
 
 
@@ -282,6 +284,10 @@ def pph_limited(wm: float, wc: float, wp: float):
     lo, hi = C.c_double(), C.c_double()
     lib().orc_pph_limited(float(wm), float(wc), float(wp), C.byref(lo), C.byref(hi))
     return lo.value, hi.value
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def num_threads() -> int:
