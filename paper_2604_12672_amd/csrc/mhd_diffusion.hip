@@ -4,13 +4,15 @@
 // The operator M[T] = (1/rho) div(K grad T) uses the harmonic mean of
 // chi = T^3 / (kappa rho) for the face conductivity K = (4 a c / 3) chi_f
 // and a power-law opacity kappa = kappa0 rho^alpha T^beta.  One kernel per
-// RKL2 stage: every cell reads T and chi of itself and its six neighbours
-// from the previous stage (two ping-pong buffers), forms M, combines the
+// RKL2 stage: every cell forms M from T and chi of itself and its six
+// neighbours of the previous stage (two ping-pong buffers), combines the
 // stage (mu, nu, mu~, gamma~ of Meyer, Balsara & Aslam), and writes its new
 // value together with its new T (Newton from the previous stage's T in the
 // internal-energy form; the value itself in the temperature form) and chi,
-// so the next stage reads them without recomputing powers.  Memory-bound
-// stencil work: coalesced SoA streams, neighbours from the caches.
+// so the next stage reads them without recomputing powers.  The stage
+// kernel marches z through column tiles with the z neighbours in registers
+// and the x/y neighbours in LDS; the other kernels are coalesced per-cell
+// streams.
 #include <hip/hip_runtime.h>
 
 #include "mhd_device.h"
@@ -21,45 +23,6 @@ namespace mhd {
 __device__ __forceinline__ double chi_of(const DiffParams &dp, double rho, double T) {
   // T^3 / (kappa0 rho^alpha T^beta rho) = T^(3 - beta) rho^(-1 - alpha) / kappa0
   return exp((3.0 - dp.beta) * log(T) - (1.0 + dp.alpha) * log(rho)) * dp.ikappa0;
-}
-
-// M[T] at cell q (times 1/c_v0 in the temperature form is left to the caller)
-__device__ __forceinline__ double diff_rhs(const Phys &ph, const DiffParams &dp,
-                                           const double *__restrict__ rho,
-                                           const double *__restrict__ T,
-                                           const double *__restrict__ chi, size_t q, int i,
-                                           int j, int k) {
-  const size_t plane = (size_t)ph.nx * ph.ny;
-  const double tq = T[q], cq = chi[q];
-  double div = 0.0;
-  // lower and upper neighbour offsets per active axis
-  auto face = [&](size_t qn, double inv_dx) {
-    // flux from q to its neighbour: -K (T_n - T_q) / dx; its divergence
-    // contribution to q is -(flux out) / dx
-    const double cn = chi[qn];
-    const double K = dp.pref * 2.0 * cq * cn * rcp<double>(cq + cn);
-    return K * (T[qn] - tq) * inv_dx * inv_dx;
-  };
-  if (ph.dims_active[0]) {
-    const int im = i == 0 ? ph.nx - 1 : i - 1, ip = i + 1 == ph.nx ? 0 : i + 1;
-    div += face(q - i + im, ph.idx) + face(q - i + ip, ph.idx);
-  }
-  if (ph.dims_active[1]) {
-    const int jm = j == 0 ? ph.ny - 1 : j - 1, jp = j + 1 == ph.ny ? 0 : j + 1;
-    div += face(q + (size_t)(jm - j) * ph.nx, ph.idy) + face(q + (size_t)(jp - j) * ph.nx, ph.idy);
-  }
-  if (ph.dims_active[2]) {
-    // a reflecting wall is insulating: no flux through it
-    if (!(ph.reflect && k == 0)) {
-      const int km = k == 0 ? ph.nz - 1 : k - 1;
-      div += face(q + ((size_t)km - (size_t)k) * plane, ph.idz);
-    }
-    if (!(ph.reflect && k + 1 == ph.nz)) {
-      const int kp = k + 1 == ph.nz ? 0 : k + 1;
-      div += face(q + ((size_t)kp - (size_t)k) * plane, ph.idz);
-    }
-  }
-  return div * rcp<double>(rho[q]);
 }
 
 // e_int, T (Newton from Tg, or the bracketed solve), c_v and chi of every
@@ -106,6 +69,15 @@ __global__ __launch_bounds__(256) void diff_init_kernel(
 // then the temperature and chi of yn.  In the temperature form (TF) the
 // stage value is the temperature: Ta is y1 itself (y0 in the first stage),
 // M is divided by c_v0, and no separate temperature is read or written.
+//
+// A block owns a 64 x 4 column tile and a z segment and marches up it: the
+// column's T and chi of planes k-1, k, k+1 stay in registers (the z
+// neighbours), the tile's plane k with a one-cell ring is staged in LDS
+// (the x and y neighbours), so T and chi are read from HBM about once.
+constexpr int DTX = 64, DTY = 4;                // tile (256 threads)
+constexpr int DLX = DTX + 2, DLY = DTY + 2;     // staged plane with its ring
+constexpr int DZSEG = 16;                       // planes per block
+
 template <bool TF>
 __global__ __launch_bounds__(256) void diff_stage_kernel(
     Phys ph, DiffParams dp, const double *__restrict__ U, const double *__restrict__ Ta,
@@ -114,35 +86,96 @@ __global__ __launch_bounds__(256) void diff_stage_kernel(
     const double *__restrict__ cv0, int first, double mu, double nu, double mut,
     double gamt, double dt, double *__restrict__ yn, double *__restrict__ Tb,
     double *__restrict__ chib, int *flags) {
-  const size_t n = (size_t)ph.nx * ph.ny * ph.nz;
+  __shared__ double sT[DLY][DLX], sC[DLY][DLX];
+  const size_t plane = (size_t)ph.nx * ph.ny;
   const double *rho = U;
   const double *yp = TF ? Ta : y1;
-  size_t c0, c1;
-  block_cells(n, c0, c1);
-  for (size_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) {
-    int i, j, k;
-    cell_ijk(ph, q, i, j, k);
-    const double r = rho[q];
-    double M = diff_rhs(ph, dp, rho, Ta, chia, q, i, j, k);
-    if (TF) M *= rcp<double>(cv0[q]);
-    double v;
-    if (first) {
-      M0[q] = M;
-      v = y0[q] + mut * dt * M;
-    } else {
-      v = mu * yp[q] + nu * y2[q] + (1.0 - mu - nu) * y0[q] + mut * dt * M + gamt * dt * M0[q];
+  const int tid = threadIdx.x;
+  const int tx = tid % DTX, ty = tid / DTX;
+  const int ntx = (ph.nx + DTX - 1) / DTX, nty = (ph.ny + DTY - 1) / DTY;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int btx = lb % ntx, bty = (lb / ntx) % nty, bz = lb / (ntx * nty);
+  const int X0 = btx * DTX, Y0 = bty * DTY;
+  const int z0 = bz * DZSEG, z1 = min(z0 + DZSEG, ph.nz);
+  const int gx = X0 + tx, gy = Y0 + ty;
+  const bool own = gx < ph.nx && gy < ph.ny;
+  const size_t col = (size_t)wrapi(gy, ph.ny) * ph.nx + wrapi(gx, ph.nx);
+  // z neighbours of the column (a wall plane's missing neighbour is never
+  // used: the wall is insulating)
+  auto zp = [&](int m) { return (size_t)wrapi(m, ph.nz) * plane + col; };
+  double tm = Ta[zp(z0 - 1)], cm = chia[zp(z0 - 1)];
+  double tc = Ta[zp(z0)], ccur = chia[zp(z0)];
+  for (int k = z0; k < z1; ++k) {
+    // the next plane's values are requested before this plane is evaluated
+    const double tn = Ta[zp(k + 1)], cn = chia[zp(k + 1)];
+    const size_t pk = (size_t)k * plane;
+    sT[ty + 1][tx + 1] = tc;
+    sC[ty + 1][tx + 1] = ccur;
+    for (int h = tid; h < DLX * DLY - DTX * DTY; h += 256) {
+      // ring cells: bottom row, top row, then left and right columns
+      int hx, hy;
+      if (h < DLX) {
+        hy = 0;
+        hx = h;
+      } else if (h < 2 * DLX) {
+        hy = DLY - 1;
+        hx = h - DLX;
+      } else {
+        const int t = h - 2 * DLX;  // 0 .. 2 DTY - 1
+        hy = 1 + t / 2;
+        hx = (t & 1) ? DLX - 1 : 0;
+      }
+      const size_t qh = pk + (size_t)wrapi(Y0 - 1 + hy, ph.ny) * ph.nx + wrapi(X0 - 1 + hx, ph.nx);
+      sT[hy][hx] = Ta[qh];
+      sC[hy][hx] = chia[qh];
     }
-    yn[q] = v;
-    double t = v;
-    if (!TF) {
-      int it, fb;
-      if (!(v > 0.0) || eos_temperature(ph, r, v, Ta[q], ph.newton_maxit, t, it, fb))
+    __syncthreads();
+    const size_t q = pk + col;
+    // M[T]: the face fluxes in the order x-, x+, y-, y+, z-, z+
+    double div = 0.0;
+    auto face = [&](double tnb, double cnb, double inv_dx) {
+      const double K = dp.pref * 2.0 * ccur * cnb * rcp<double>(ccur + cnb);
+      return K * (tnb - tc) * inv_dx * inv_dx;
+    };
+    if (ph.dims_active[0])
+      div += face(sT[ty + 1][tx], sC[ty + 1][tx], ph.idx) +
+             face(sT[ty + 1][tx + 2], sC[ty + 1][tx + 2], ph.idx);
+    if (ph.dims_active[1])
+      div += face(sT[ty][tx + 1], sC[ty][tx + 1], ph.idy) +
+             face(sT[ty + 2][tx + 1], sC[ty + 2][tx + 1], ph.idy);
+    if (ph.dims_active[2]) {
+      if (!(ph.reflect && k == 0)) div += face(tm, cm, ph.idz);
+      if (!(ph.reflect && k + 1 == ph.nz)) div += face(tn, cn, ph.idz);
+    }
+    if (own) {
+      const double r = rho[q];
+      double M = div * rcp<double>(r);
+      if (TF) M *= rcp<double>(cv0[q]);
+      double v;
+      if (first) {
+        M0[q] = M;
+        v = y0[q] + mut * dt * M;
+      } else {
+        v = mu * yp[q] + nu * y2[q] + (1.0 - mu - nu) * y0[q] + mut * dt * M +
+            gamt * dt * M0[q];
+      }
+      yn[q] = v;
+      double t = v;
+      if (!TF) {
+        int it, fb;
+        if (!(v > 0.0) || eos_temperature(ph, r, v, tc, ph.newton_maxit, t, it, fb))
+          atomicOr(flags, 2);
+        Tb[q] = t;
+      } else if (!(v > 0.0)) {
         atomicOr(flags, 2);
-      Tb[q] = t;
-    } else if (!(v > 0.0)) {
-      atomicOr(flags, 2);
+      }
+      chib[q] = chi_of(dp, r, t);
     }
-    chib[q] = chi_of(dp, r, t);
+    __syncthreads();
+    tm = tc;
+    cm = ccur;
+    tc = tn;
+    ccur = cn;
   }
 }
 
@@ -247,12 +280,14 @@ hipError_t launch_diff_stage(const Ctx &c, const double *U, const double *Ta, co
                              double *Tb, double *chib, int tform, int first, double mu,
                              double nu, double mut, double gamt, double dt) {
   const DiffBufs &d = c.diff;
+  const dim3 grid(((c.ph.nx + DTX - 1) / DTX) * ((c.ph.ny + DTY - 1) / DTY) *
+                  ((c.ph.nz + DZSEG - 1) / DZSEG));
   if (tform)
-    hipLaunchKernelGGL(diff_stage_kernel<true>, dim3(grid_blocks(c)), dim3(256), 0, c.stream,
+    hipLaunchKernelGGL(diff_stage_kernel<true>, grid, dim3(256), 0, c.stream,
                        c.ph, c.dparams, U, Ta, chia, y0, y1, y2, d.M0, d.cv0, first, mu, nu,
                        mut, gamt, dt, yn, Tb, chib, c.flags);
   else
-    hipLaunchKernelGGL(diff_stage_kernel<false>, dim3(grid_blocks(c)), dim3(256), 0, c.stream,
+    hipLaunchKernelGGL(diff_stage_kernel<false>, grid, dim3(256), 0, c.stream,
                        c.ph, c.dparams, U, Ta, chia, y0, y1, y2, d.M0, d.cv0, first, mu, nu,
                        mut, gamt, dt, yn, Tb, chib, c.flags);
   return hipGetLastError();
