@@ -53,7 +53,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "aad38bc607c6a088": {"fp64": (1475465.2, 1105324.1), "split": (1826347.3, 1217748.4)},
+    "9af9f809915e2b2b": {"fp64": (1474659.4, 1105122.3), "split": (1826587.3, 1216364.5)},
 }
 
 

@@ -429,6 +429,8 @@ int mhd_set_state(mhd_ctx *h, const double *U, const double *Bx, const double *B
                                              c.T[c.tcur]));
   }
   c.have_state = true;
+  c.t0_current = false;
+  c.p_current = false;
   c.have_species = false;
   return latched(h);
 }
@@ -454,6 +456,25 @@ int mhd_get_species(mhd_ctx *h, double *rhoX, int32_t where) {
   HIPCHK(h, hipMemcpyAsync(rhoX, c.X[c.cur], sizeof(double) * c.d.nspecies * c.ncell,
                            kind_out(where), c.stream));
   return latched(h);
+}
+
+// The CFL kernel of the current state; with the gas+radiation EOS it also
+// stores the converged temperatures where the first stage looks for its
+// guess (the previous-T array, or the learned guess array, which then needs
+// no guess kernel for that stage), and with flattening the pressure the
+// first stage's detector needs.
+static hipError_t launch_cfl(mhd::Ctx &c, double cfl) {
+  const int n = c.cur;
+  const bool learned = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP;
+  double *Tout = c.ph.gasrad ? (learned ? c.T[0] : c.T[c.tcur]) : nullptr;
+  hipError_t e = mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
+                                          c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev,
+                                          Tout, c.d.flatten ? c.shock_p : nullptr);
+  if (e == hipSuccess) {
+    c.t0_current = learned;
+    c.p_current = c.d.flatten != 0;
+  }
+  return e;
 }
 
 static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
@@ -488,9 +509,12 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.Bzo = c.Bz[o];
     const bool prev_t = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_PREV_T;
     const bool learned = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP;
-    if (learned) {
+    const bool reuse = s == 0 && (!learned || c.t0_current) && (!c.d.flatten || c.p_current);
+    if (learned && !(reuse && c.t0_current)) {
       // learned guesses of the stage input, polished by Newton in the stage
-      // (with flattening already here, where the pressure is taken too)
+      // (with flattening already here, where the pressure is taken too);
+      // the first stage skips this when the CFL kernel left the converged
+      // temperatures of its input
       HIPCHK(h, mhd::launch_mlp_guess(c, p.Us, p.Bxs, p.Bys, p.Bzs, c.T[0],
                                       c.d.flatten ? c.shock_p : nullptr));
     }
@@ -499,7 +523,7 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.newton_cap = learned ? c.ph.newton_maxit_mlp : c.ph.newton_maxit;
     if (c.d.flatten) {
       // flags of the stage input, from the same EOS guess the stage uses
-      if (!learned)
+      if (!learned && !reuse)
         HIPCHK(h, mhd::launch_shock_pressure(c, p.Us, p.Bxs, p.Bys, p.Bzs, p.Tin, p.newton_cap));
       HIPCHK(h, mhd::launch_shock_flags(c));
       p.flat = c.shock_f;
@@ -524,6 +548,8 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     in = o;
   }
   c.cur = in;
+  c.t0_current = false;
+  c.p_current = false;
   return MHD_OK;
 }
 
@@ -543,9 +569,7 @@ int mhd_advance(mhd_ctx *h, double cfl, int32_t nsteps) {
   if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   for (int s = 0; s < nsteps; ++s) {
-    const int n = c.cur;
-    HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
-                                       c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev));
+    HIPCHK(h, launch_cfl(c, cfl));
     int rc = run_step(h, 0.0, c.dt_dev);
     if (rc) return rc;
   }
@@ -559,9 +583,7 @@ int mhd_compute_dt(mhd_ctx *h, double cfl, double *dt_out) {
   if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(h, MHD_ERR_ARG, "cfl must be > 0");
   if (c.d.eos_guess == MHD_GUESS_MLP && !c.have_mlp)
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
-  const int n = c.cur;
-  HIPCHK(h, mhd::launch_signal_speed(c, c.U[n], c.Bx[n], c.By[n], c.Bz[n],
-                                     c.ph.gasrad ? c.T[c.tcur] : nullptr, cfl, c.dt_dev));
+  HIPCHK(h, launch_cfl(c, cfl));
   double dt = 0.0;
   HIPCHK(h, hipMemcpyAsync(&dt, c.dt_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
   int rc = latched(h);
@@ -709,6 +731,9 @@ int mhd_set_eos_mlp(mhd_ctx *h, const float *w1, const float *b1, const uint16_t
   c.ph.mlp_b3 = b3;
   c.ph.mlp_inv_sT = (float)(1.0 / norm[5]);
   c.have_mlp = true;
+  // temperatures and pressures left by a CFL kernel came from the old network
+  c.t0_current = false;
+  c.p_current = false;
   return MHD_OK;
 }
 
@@ -839,6 +864,8 @@ int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts
   }
   const double *Tlast = tform ? p1 : d.T[ta];
   HIPCHK(h, mhd::launch_diff_finish(c, c.U[s], p1, Tlast, tform, prev_t ? c.T[c.tcur] : nullptr));
+  c.t0_current = false;
+  c.p_current = false;
   return MHD_OK;
 }
 

@@ -112,6 +112,12 @@ struct Ctx {
   double *X[3] = {nullptr, nullptr, nullptr};
   double *mf[3] = {nullptr, nullptr, nullptr};
   bool have_species = false;
+  // learned guess: T[0] holds the converged temperature of the current
+  // state (left by the CFL kernel), so the first stage needs no guess kernel
+  bool t0_current = false;
+  // flattening: shock_p holds the pressure of the current state (also left
+  // by the CFL kernel), so the first stage needs no pressure pass
+  bool p_current = false;
   int zseg = 32;
   std::string err;
 };
@@ -119,9 +125,13 @@ struct Ctx {
 // launchers (mhd_kernels.hip)
 hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
                         double cc, double dt_host);
+// the CFL step into dt_dev; with Tout (gas+radiation, nullable) the
+// converged temperature of every cell is stored there as well, with Pout
+// (nullable) the thermal pressure
 hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz,
-                               const double *T, double cfl, double *dt_dev);
+                               const double *T, double cfl, double *dt_dev,
+                               double *Tout = nullptr, double *Pout = nullptr);
 hipError_t launch_init_temperature(const Ctx &c, const double *U,
                                    const double *Bx, const double *By,
                                    const double *Bz, const double *Tg, double *T);

@@ -738,7 +738,7 @@ __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
     Phys ph, const double *__restrict__ U, const double *__restrict__ Bx,
     const double *__restrict__ By, const double *__restrict__ Bz,
     const double *__restrict__ T, const void *mlp, double *__restrict__ partial,
-    int *flags) {
+    int *flags, double *__restrict__ Tout, double *__restrict__ Pout) {
   __shared__ __attribute__((aligned(16))) char sMlpRaw[ML ? sizeof(MlpLds) : 16];
   const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
   if (ML) {
@@ -777,6 +777,9 @@ __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
     cons2prim<GR>(ph, u, b, tg, zero, o, ML ? ph.newton_maxit_mlp : ph.newton_maxit);
     if (!valid) continue;
     bad |= o.bad;
+    // the converged temperature is the best guess the next stage can get
+    if (GR && Tout) Tout[q] = o.T;
+    if (Pout) Pout[q] = o.w[Q_P];  // thermal pressure for the flattening detector
     const double rho = u[0];
     const double P = o.w[Q_P];
     const double a2 = o.w[Q_GC] * P / rho;
@@ -830,19 +833,20 @@ __global__ void finish_dt_kernel(const double *__restrict__ partial, int nb,
 
 hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz,
-                               const double *T, double cfl, double *dt_dev) {
+                               const double *T, double cfl, double *dt_dev, double *Tout,
+                               double *Pout) {
   const size_t n = c.ncell;
   int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
   nb = nb < RED_BLOCKS ? nb : RED_BLOCKS;
   if (!c.ph.gasrad)
     hipLaunchKernelGGL((signal_speed_kernel<false, false>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, nullptr, Pout);
   else if (c.d.eos_guess == MHD_GUESS_MLP)
     hipLaunchKernelGGL((signal_speed_kernel<true, true>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, Tout, Pout);
   else
     hipLaunchKernelGGL((signal_speed_kernel<true, false>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags);
+                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, Tout, Pout);
   hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(RED_THREADS), 0, c.stream, c.red, nb, cfl,
                      dt_dev, c.red + RED_BLOCKS);
   return hipGetLastError();
