@@ -71,7 +71,14 @@ CASES = [((20, 17, 13), 0, 1, False, dict()),
          ((19, 15, 14), 1, 3, False, dict(recon=orc.RECON_PPH, rk_order=3)),
          ((20, 17, 13), 0, 12, True, dict(recon=orc.RECON_PPH, rk_order=3, flatten=1)),
          ((19, 15, 14), 1, 5, True, dict(flatten=1)),
-         ((1, 24, 9), 0, 4, False, dict(recon=orc.RECON_PPH))]
+         ((1, 24, 9), 0, 4, False, dict(recon=orc.RECON_PPH)),
+         # walls with three z segments of the species kernel (32, 32, 6
+         # planes), a ragged y tile and the largest species count
+         ((18, 9, 70), 1, 16, True, dict(recon=orc.RECON_PPH, rk_order=3, flatten=1)),
+         # one cell along y; two z segments
+         ((33, 1, 40), 0, 8, False, dict()),
+         # one cell along z
+         ((17, 10, 1), 0, 6, False, dict(rk_order=3))]
 
 
 @pytest.mark.parametrize("shape,bcz,ns,blast,kw", CASES)
