@@ -53,7 +53,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "9af9f809915e2b2b": {"fp64": (1474659.4, 1105122.3), "split": (1826587.3, 1216364.5)},
+    "6a43812bcf32f285": {"fp64": (1500153.7, 1106756.2), "split": (1838707.4, 1212893.1)},
 }
 
 

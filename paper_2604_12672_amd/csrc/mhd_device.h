@@ -392,8 +392,7 @@ struct FaceBg {
 
 template <typename R>
 struct SideQ {  // derived side quantities
-  R rho, vn, v1, v2, pt, b1, b2, E, vb;
-  R F[7];
+  R rho, vn, v1, v2, pt, b1, b2;
 };
 
 // Reciprocals of two numbers.  FP64: one hardware reciprocal with its
@@ -411,13 +410,12 @@ __device__ __forceinline__ void rcp2(R a, R b, R &ia, R &ib) {
   }
 }
 
-// Side quantities from the reconstructed deviations; ir = 1/rho and
-// igm = 1/(gamma_e - 1) come from the caller (taken for both sides at
-// once).  Returns the fast speed along the normal, c_s^2 and |v|^2.
+// Side quantities from the reconstructed deviations; ir = 1/rho comes from
+// the caller (taken for both sides at once).  Returns the fast speed along
+// the normal, c_s^2 and |v|^2.
 template <typename R, bool GR>
 __device__ __forceinline__ void side_prep(const Side<R> &s, R bn, const FaceBg<R> &bg, R rho,
-                                          R ir, R igm, R gam, SideQ<R> &q, R &cf, R &cs2,
-                                          R &v2) {
+                                          R ir, R gam, SideQ<R> &q, R &cf, R &cs2, R &v2) {
   q.rho = rho;
   q.vn = s.vn;
   q.v1 = s.v1;
@@ -430,21 +428,32 @@ __device__ __forceinline__ void side_prep(const Side<R> &s, R bn, const FaceBg<R
   v2 = s.vn * s.vn + s.v1 * s.v1 + s.v2 * s.v2;
   const R gc = GR ? bg.gc + s.dgc : gam;
   q.pt = s.dp + R(0.5) * B2;  // p_T - P_hat
-  q.E = P * igm + R(0.5) * rho * v2 + R(0.5) * B2;
   cs2 = gc * P * ir;
   const R a2b2 = cs2 + B2 * ir;
   // discriminant clipped at zero against rounding (fmax: also maps NaN to 0)
   const R disc = fmax(a2b2 * a2b2 - R(4) * cs2 * bn2 * ir, R(0));
   cf = sqroot<R>(R(0.5) * (a2b2 + sqroot<R>(disc)));
-  q.vb = s.vn * bn + s.v1 * s.b1 + s.v2 * s.b2;
+}
+
+// Total energy, v.B and the physical flux (deviation form) of one side;
+// igm = 1/(gamma_e - 1), v2 = |v|^2 and pt = p_T - P_hat as from side_prep.
+// The LHLLD solver needs them for the side it selects only.
+template <typename R>
+__device__ __forceinline__ void side_flux(const Side<R> &s, R bn, const FaceBg<R> &bg, R rho,
+                                          R igm, R v2, R pt, R &E, R &vb, R F[7]) {
+  const R P = bg.p + s.dp;
+  const R bn2 = bn * bn;
+  const R B2 = bn2 + s.b1 * s.b1 + s.b2 * s.b2;
+  E = P * igm + R(0.5) * rho * v2 + R(0.5) * B2;
+  vb = s.vn * bn + s.v1 * s.b1 + s.v2 * s.b2;
   const R rv = rho * s.vn;
-  q.F[0] = rv;
-  q.F[1] = rv * s.vn + q.pt - bn2;
-  q.F[2] = rv * s.v1 - bn * s.b1;
-  q.F[3] = rv * s.v2 - bn * s.b2;
-  q.F[4] = (q.E + bg.p + q.pt) * s.vn - bn * q.vb;
-  q.F[5] = s.vn * s.b1 - bn * s.v1;
-  q.F[6] = s.vn * s.b2 - bn * s.v2;
+  F[0] = rv;
+  F[1] = rv * s.vn + pt - bn2;
+  F[2] = rv * s.v1 - bn * s.b1;
+  F[3] = rv * s.v2 - bn * s.b2;
+  F[4] = (E + bg.p + pt) * s.vn - bn * vb;
+  F[5] = s.vn * s.b1 - bn * s.v1;
+  F[6] = s.vn * s.b2 - bn * s.v2;
 }
 
 template <typename R>
@@ -494,8 +503,8 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   if (GR) rcp2<R>(bg.ge + L.dge - R(1), bg.ge + Rt.dge - R(1), igL, igR);
   SideQ<R> qL, qR;
   R cfL, cfR, csL, csR, v2L, v2R;
-  side_prep<R, GR>(L, bn, bg, rhoL, irL, igL, gam, qL, cfL, csL, v2L);
-  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, igR, gam, qR, cfR, csR, v2R);
+  side_prep<R, GR>(L, bn, bg, rhoL, irL, gam, qL, cfL, csL, v2L);
+  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, gam, qR, cfR, csR, v2R);
   const R cmax = fmax(cfL, cfR);
   const R SL = fmin(qL.vn, qR.vn) - cmax;
   const R SR = fmax(qL.vn, qR.vn) + cmax;
@@ -572,16 +581,23 @@ __device__ __forceinline__ void riemann(const Side<R> &L, const Side<R> &Rt,
   const R db1 = sel(lf, sL.db1, sR.db1), db2 = sel(lf, sL.db2, sR.db2);
   const R vs1 = sel(lf, vL1, vR1), vs2 = sel(lf, vL2, vR2);
   const R bs1 = sel(lf, bL1, bR1), bs2 = sel(lf, bL2, bR2);
+  // energy, v.B and flux of the selected side
+  const R pt = sel(lf, qL.pt, qR.pt), vn = sel(lf, qL.vn, qR.vn);
+  Side<R> sa;
+  sa.vn = vn;
+  sa.v1 = sel(lf, qL.v1, qR.v1);
+  sa.v2 = sel(lf, qL.v2, qR.v2);
+  sa.b1 = sel(lf, qL.b1, qR.b1);
+  sa.b2 = sel(lf, qL.b2, qR.b2);
+  sa.dp = sel(lf, L.dp, Rt.dp);
+  R E, vb, Fa[7];
+  side_flux<R>(sa, bn, bg, rho, sel(lf, igL, igR), sel(lf, v2L, v2R), pt, E, vb, Fa);
   // E* - E of the selected side:
   // [(S_M - v_n)(E + P_hat) + p~* S_M - p~ v_n + B_n (v.B - v*.B*)] / (S - S_M)
-  const R E = sel(lf, qL.E, qR.E), pt = sel(lf, qL.pt, qR.pt), vn = sel(lf, qL.vn, qR.vn);
-  const R vb = sel(lf, qL.vb, qR.vb), isd = sel(lf, sL.isd, sR.isd);
+  const R isd = sel(lf, sL.isd, sR.isd);
   const R dvn = sel(lf, sL.dvn, sR.dvn);
   const R vbs = SM * bn + vs1 * bs1 + vs2 * bs2;
   const R dE = (dvn * (E + bg.p) + pst * SM - pt * vn + bn * (vb - vbs)) * isd;
-  R Fa[7];
-#pragma unroll
-  for (int c = 0; c < 7; ++c) Fa[c] = sel(lf, qL.F[c], qR.F[c]);
   // single-star flux F* = F + S (U* - U); the interface pressure p~*
   // carries the low-dissipation factor into the normal momentum;
   // double-star flux F** = F* + S* (U** - U*)
@@ -621,8 +637,11 @@ __device__ __forceinline__ void hll_flux(const Side<R> &L, const Side<R> &Rt, R 
   if (GR) rcp2<R>(bg.ge + L.dge - R(1), bg.ge + Rt.dge - R(1), igL, igR);
   SideQ<R> qL, qR;
   R cfL, cfR, csL, csR, v2L, v2R;
-  side_prep<R, GR>(L, bn, bg, rhoL, irL, igL, gam, qL, cfL, csL, v2L);
-  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, igR, gam, qR, cfR, csR, v2R);
+  side_prep<R, GR>(L, bn, bg, rhoL, irL, gam, qL, cfL, csL, v2L);
+  side_prep<R, GR>(Rt, bn, bg, rhoR, irR, gam, qR, cfR, csR, v2R);
+  R EL, ER, vbL, vbR, FL[7], FR[7];
+  side_flux<R>(L, bn, bg, rhoL, igL, v2L, qL.pt, EL, vbL, FL);
+  side_flux<R>(Rt, bn, bg, rhoR, igR, v2R, qR.pt, ER, vbR, FR);
   const R cmax = fmax(cfL, cfR);
   const R SL = fmin(qL.vn, qR.vn) - cmax;
   const R SR = fmax(qL.vn, qR.vn) + cmax;
@@ -641,8 +660,8 @@ __device__ __forceinline__ void hll_flux(const Side<R> &L, const Side<R> &Rt, R 
   const bool outL = R(0) <= SL, outR = SR < R(0);
 #pragma unroll
   for (int c = 0; c < 7; ++c) {
-    const R fh = (SR * qL.F[c] - SL * qR.F[c] + SL * SR * dU[c]) * iw;
-    F[c] = outL ? qL.F[c] : (outR ? qR.F[c] : fh);
+    const R fh = (SR * FL[c] - SL * FR[c] + SL * SR * dU[c]) * iw;
+    F[c] = outL ? FL[c] : (outR ? FR[c] : fh);
   }
 }
 
