@@ -57,10 +57,21 @@ TRAFFIC_KIB = {
 }
 
 
+# VALU wave instructions per stage dispatch (SQ_INSTS_VALU summed over the
+# chip, from profiles/stage_kernel_stratified256_issue_counters.md) for the
+# digest of the stage sources.  At the chip's issue rate (1024 SIMDs, one
+# wave64 instruction per four cycles, 2.4 GHz) they give the launch's
+# instruction-issue floor: the bound the stage kernel actually meets.
+VALU_INSTS = {
+    "6a43812bcf32f285": {"fp64": 944107393, "split": 640723719},
+}
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
+
+
 # HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch, averaged over a super step) for the digest of its sources
 RKL2_TRAFFIC_KIB = {
-    "796567234660813b": {"eint": (501498.8, 397803.5), "temp": (517011.6, 266731.5)},
+    "6bbdb93c6e68289d": {"eint": (501495.7, 397803.5), "temp": (518452.3, 266731.5)},
 }
 
 
@@ -144,11 +155,17 @@ def roofline(w, stage_ms, path, learned=False):
     per_launch = per_zone * w.ncells
     achieved = per_launch / (stage_ms * 1e-3) / 1e9
     tr = traffic_bytes(path)
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if tr is None else round(tr),
-            "kernel": "stage_kernel", "stage_ms": round(stage_ms, 4),
-            "bytes_per_zone_stage": per_zone, "algorithmic_bytes_per_launch": round(per_launch)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if tr is None else round(tr),
+           "kernel": "stage_kernel", "stage_ms": round(stage_ms, 4),
+           "bytes_per_zone_stage": per_zone, "algorithmic_bytes_per_launch": round(per_launch)}
+    n = VALU_INSTS.get(kernel_digest(), {}).get(path)
+    if n is not None:
+        floor_ms = n / VALU_ISSUE_PER_S * 1e3
+        out["valu_issue"] = {"wave_insts_per_launch": n, "floor_ms": round(floor_ms, 4),
+                             "frac": round(floor_ms / stage_ms, 4)}
+    return out
 
 
 def newton_stats(w, diag, stages=2):
