@@ -53,7 +53,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "6a43812bcf32f285": {"fp64": (1500153.7, 1106756.2), "split": (1838707.4, 1212893.1)},
+    "c1b441fbe5ee8805": {"fp64": (1484668.0, 1107636.5), "split": (1836720.7, 1218368.7)},
 }
 
 
@@ -63,7 +63,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "6a43812bcf32f285": {"fp64": 944107393, "split": 640723719},
+    "c1b441fbe5ee8805": {"fp64": 899774355, "split": 640723719},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
@@ -71,7 +71,7 @@ VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 # HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch, averaged over a super step) for the digest of its sources
 RKL2_TRAFFIC_KIB = {
-    "6bbdb93c6e68289d": {"eint": (501495.7, 397803.5), "temp": (518452.3, 266731.5)},
+    "c14bb0c72755b560": {"eint": (501483.1, 397803.5), "temp": (517077.8, 266731.5)},
 }
 
 
