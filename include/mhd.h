@@ -261,6 +261,19 @@ int mhd_destroy(mhd_ctx *ctx);
 int mhd_launch_info(const mhd_ctx *ctx, int32_t *tile, int32_t *zseg,
                     int32_t *blocks);
 
+/* Accuracy check of the device arithmetic (for tests): evaluates, for each
+   of the n device doubles x[i] > 0, the reciprocal and square root the
+   kernels use, into the device array out of 4 n doubles:
+     out[i]       1/x, the EOS / primitive / update reciprocal
+                  (refined hardware seed, within half an ulp)
+     out[n+i]     1/x, the flux-arithmetic reciprocal (one refinement step)
+     out[2n+i]    sqrt(x), the full sequence
+     out[3n+i]    sqrt(x), the flux-arithmetic one (one refinement step)
+   hip_stream: the stream to run on (NULL: the default stream); the call
+   synchronises it.  Returns MHD_ERR_ARG for n < 0 or NULL arrays with
+   n > 0, MHD_ERR_HIP if the launch fails. */
+int mhd_math_check(const double *x, double *out, int64_t n, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -160,6 +160,11 @@ int latched(mhd_ctx *h) {
 
 }  // namespace
 
+namespace mhd {
+// accuracy check of the device reciprocal / square root (mhd_mathcheck.hip)
+hipError_t launch_math_check(hipStream_t s, const double *x, double *out, long long n);
+}  // namespace mhd
+
 extern "C" {
 
 int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
@@ -867,6 +872,14 @@ int mhd_diffuse(mhd_ctx *h, double dt, int32_t nsts, int32_t mode, int32_t *nsts
   c.t0_current = false;
   c.p_current = false;
   return MHD_OK;
+}
+
+int mhd_math_check(const double *x, double *out, int64_t n, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return MHD_ERR_ARG;
+  if (n == 0) return MHD_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (mhd::launch_math_check(s, x, out, (long long)n) != hipSuccess) return MHD_ERR_HIP;
+  return hipStreamSynchronize(s) == hipSuccess ? MHD_OK : MHD_ERR_HIP;
 }
 
 int mhd_launch_info(const mhd_ctx *h, int32_t *tile, int32_t *zseg, int32_t *blocks) {

@@ -60,7 +60,8 @@ EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eo
            "mhd_eos_solve", "mhd_set_state", "mhd_compute_dt", "mhd_step", "mhd_advance",
            "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
            "mhd_shock_flags", "mhd_set_species", "mhd_get_species",
-           "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse"]
+           "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse",
+           "mhd_math_check"]
 
 _lib = None
 
@@ -97,6 +98,7 @@ def load():
     L.mhd_last_error.argtypes = [vp]
     L.mhd_last_error.restype = C.c_char_p
     L.mhd_destroy.argtypes = [vp]
+    L.mhd_math_check.argtypes = [vp, vp, C.c_int64, vp]
     L.mhd_launch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]
     L.mhd_set_opacity.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
@@ -164,6 +166,22 @@ def _where(*arrays):
     if len(kinds) > 1:
         raise ValueError("mixed host/device arguments")
     return kinds.pop() if kinds else HOST
+
+
+def math_check(x):
+    """Device reciprocal and square root of the kernels at the positive
+    doubles x (a CUDA tensor): a (4, n) tensor of 1/x (EOS, primitives,
+    updates), 1/x (flux arithmetic), sqrt(x) (full), sqrt(x) (flux
+    arithmetic)."""
+    import torch
+    L = load()
+    x = x.contiguous()
+    out = torch.empty((4, x.numel()), dtype=torch.float64, device=x.device)
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    rc = L.mhd_math_check(x.data_ptr(), out.data_ptr(), x.numel(), stream)
+    if rc != 0:
+        raise MHDError(rc, "mhd_math_check failed")
+    return out
 
 
 class Grid:

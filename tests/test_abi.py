@@ -112,3 +112,9 @@ def test_null_handles_are_rejected(lib):
     assert lib.mhd_sync(None) == -1
     assert lib.mhd_destroy(None) == 0
     assert lib.mhd_init_grid(None, None, None) == -1
+
+
+def test_math_check_validates_before_launching(lib):
+    assert lib.mhd_math_check(None, None, -1, None) == -1
+    assert lib.mhd_math_check(None, None, 5, None) == -1
+    assert lib.mhd_math_check(None, None, 0, None) == 0
