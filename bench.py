@@ -53,7 +53,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "c1b441fbe5ee8805": {"fp64": (1484668.0, 1107636.5), "split": (1836720.7, 1218368.7)},
+    "aba9d0b134a09e97": {"fp64": (1484746.6, 1107937.6), "split": (1836621.0, 1223248.9)},
 }
 
 
@@ -63,7 +63,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "c1b441fbe5ee8805": {"fp64": 899774355, "split": 640723719},
+    "aba9d0b134a09e97": {"fp64": 911465283, "split": 624704211},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 

@@ -234,7 +234,10 @@ __device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, i
   for (int i = tid; i < (int)(sizeof(MlpLds) / 16); i += nthreads) d4[i] = s4[i];
 }
 
-template <typename R, bool GR>
+// XF: the optional features of a stage (forcing field, shock-flattening
+// flags, species mass fluxes); the variant without them carries none of
+// their code, pointers or registers.
+template <typename R, bool GR, bool XF>
 __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
     int zseg) {
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           bx0 = p.Bx0[qc];
           by0 = p.By0[qc];
         }
-        if (p.force) {
+        if (XF && p.force) {
           fo[0] = p.force[qc];
           fo[1] = p.force[ncell + qc];
           fo[2] = p.force[2 * ncell + qc];
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       const int q = k + 2;
       int mir;
       const int kk = zsource(ph, q, mir);
-      if (p.flat) fn = p.flat[(size_t)kk * plane + colq];
+      if (XF && p.flat) fn = p.flat[(size_t)kk * plane + colq];
       R *sWn = &sW[q & 1][0][0];
       CellLoad c, rc;
       if (PREFETCH) {
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       }
       if (k >= z0 - 2) {
         Side<R> botn, topn;
-        const bool pphc = pph && !fc;
+        const bool pphc = pph && !(XF && fc);
         recon_cell<R, GR>(2, Wm, Wc, Wn, botn, topn, pphc);
         if (k >= z0 - 1) {
           const int fzi = zface(ph, k + 1);
@@ -467,12 +470,12 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           bzf = p.Bzs[(size_t)fzi * plane + colq];
           const R bzn = (R)bzf;
           R fz[7];
-          face_flux<R, GR>((fk | fc) != 0, topk, botn, bzn, bgf, gam, igm1, ph.xi_mode, mcut,
-                           imcut, fz);
+          face_flux<R, GR>(XF && (fk | fc) != 0, topk, botn, bzn, bgf, gam, igm1, ph.xi_mode,
+                           mcut, imcut, fz);
           // mass flux for the species: the lower face of cell k+1 (and the
           // top wall), written once, by the block that owns the cell
           const int f = k + 1;
-          if (p.mfz && owner && ((f >= z0 && f < z1) || (ph.reflect && f == ph.nz)))
+          if (XF && p.mfz && owner && ((f >= z0 && f < z1) || (ph.reflect && f == ph.nz)))
             p.mfz[(size_t)f * plane + colq] = (double)fz[0];
           to_cons<R>(2, fz, fzc);
           zf_ey = -fz[5];  // z-face E_y = -F_z[B_x]
@@ -502,7 +505,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         Side<R> yh;
         recon_cell<R, GR>(1, a, Wc, b, yl, yh, pphc);
         side_store<R, GR>(sYR, tid, yh);
-        sFL[tid] = fc;
+        if (XF) sFL[tid] = fc;
         // cell reference EMF -(v x B) of plane k+1
         rx = -(Wc[Q_VY] * Wc[Q_BZ] - Wc[Q_VZ] * Wc[Q_BY]);
         ry = -(Wc[Q_VZ] * Wc[Q_BX] - Wc[Q_VX] * Wc[Q_BZ]);
@@ -522,10 +525,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       bgc.p = (R)sBc[1][jc];
       bgc.ge = (R)sBc[2][jc];
       bgc.gc = (R)sBc[3][jc];
-      const bool hx = (fc | dpp_shr1(fc)) != 0;  // cells ci-1 and ci
+      const bool hx = XF && (fc | dpp_shr1(fc)) != 0;  // cells ci-1 and ci
       face_flux<R, GR>(hx, xll, xl, bxf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fx);
       const Side<R> yll = side_load<R, GR>(sYR, tdn);
-      const bool hy = (fc | sFL[tdn]) != 0;  // cells cj-1 and cj
+      const bool hy = XF && (fc | sFL[tdn]) != 0;  // cells cj-1 and cj
       face_flux<R, GR>(hy, yll, yl, byf_c, bgc, gam, igm1, ph.xi_mode, mcut, imcut, fy);
       R fyc[5];
       to_cons<R>(1, fy, fyc);
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       for (int f = 0; f < 5; ++f) sYF[f][tid] = fyc[f];
       // mass fluxes for the species: the lower x and y faces of the owned
       // cells of plane k+1
-      if (p.mfx && owner && k + 1 >= z0 && k + 1 < z1) {
+      if (XF && p.mfx && owner && k + 1 >= z0 && k + 1 < z1) {
         const size_t qf = (size_t)(k + 1) * plane + colq;
         p.mfx[qf] = (double)fx[0];
         p.mfy[qf] = (double)fy[0];
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         const int jk = k - (z0 - 2);
         double s1 = 0.0, s2 = 0.0, s3 = (us[0] - sBc[0][jk]) * ph.gz;
         double s4 = us[3] * ph.gz + sBc[4][jk];
-        if (p.force) {
+        if (XF && p.force) {
           s1 += us[0] * fo[0];
           s2 += us[0] * fo[1];
           s3 += us[0] * fo[2];
@@ -687,23 +690,37 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
 
 size_t mlp_bytes() { return sizeof(MlpLds); }
 
-template <typename R>
-static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b, double cc,
+template <typename R, bool GR>
+static void launch_stage_g(const Ctx &c, const StagePtrs &p, double a, double b, double cc,
                            double dt_host, dim3 grid) {
-  const Phys &ph = c.ph;
   dim3 block(NTHREADS);
-  if (!ph.gasrad)
-    hipLaunchKernelGGL((stage_kernel<R, false>), grid, block, 0, c.stream, ph, p, a, b, cc,
+  if (p.force || p.flat || p.mfx || p.mfy || p.mfz)
+    hipLaunchKernelGGL((stage_kernel<R, GR, true>), grid, block, 0, c.stream, c.ph, p, a, b, cc,
                        dt_host, c.zseg);
   else
-    hipLaunchKernelGGL((stage_kernel<R, true>), grid, block, 0, c.stream, ph, p, a, b, cc,
-                       dt_host, c.zseg);
+    hipLaunchKernelGGL((stage_kernel<R, GR, false>), grid, block, 0, c.stream, c.ph, p, a, b,
+                       cc, dt_host, c.zseg);
 }
 
 template <typename R>
+static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b, double cc,
+                           double dt_host, dim3 grid) {
+  if (!c.ph.gasrad)
+    launch_stage_g<R, false>(c, p, a, b, cc, dt_host, grid);
+  else
+    launch_stage_g<R, true>(c, p, a, b, cc, dt_host, grid);
+}
+
+// the variant the context's stages run (occupancy for the segment length;
+// a forcing field set later only changes the variant, not the result)
+template <typename R>
 static const void *stage_fn(const Ctx &c) {
-  if (!c.ph.gasrad) return reinterpret_cast<const void *>(&stage_kernel<R, false>);
-  return reinterpret_cast<const void *>(&stage_kernel<R, true>);
+  const bool xf = c.d.flatten || c.d.nspecies > 0;
+  if (!c.ph.gasrad)
+    return xf ? reinterpret_cast<const void *>(&stage_kernel<R, false, true>)
+              : reinterpret_cast<const void *>(&stage_kernel<R, false, false>);
+  return xf ? reinterpret_cast<const void *>(&stage_kernel<R, true, true>)
+            : reinterpret_cast<const void *>(&stage_kernel<R, true, false>);
 }
 
 int stage_blocks_per_cu(const Ctx &c) {
