@@ -28,3 +28,34 @@ def test_bench_runs_on_one_gpu_only(args, env):
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_algorithmic_bytes_of_the_roofline():
+    """The per-zone byte counts behind bench.py's rooflines, counted array
+    by array: a state is 5 cell + 3 face doubles (64 B); stage 1 of an
+    SSP-RK scheme reads U^n and writes U^(1), every later stage reads U^n and
+    U^(s) and writes one state; the previous-T guess reads and writes T, the
+    learned guess reads its array, a forcing field adds 3 doubles read."""
+    import types
+
+    import bench
+    state = 64.0
+
+    def w(rk, T=False, force=False):
+        return types.SimpleNamespace(params={"rk_order": rk}, T=object() if T else None,
+                                     force=object() if force else None)
+
+    rk2 = ((state + state) + (2 * state + state)) / 2
+    rk3 = ((state + state) + 2 * (2 * state + state)) / 3
+    assert bench.stage_bytes(w(2), False) == rk2 == 160.0
+    assert bench.stage_bytes(w(3), False) == pytest.approx(rk3)
+    assert bench.stage_bytes(w(2, T=True), False) == rk2 + 16.0
+    assert bench.stage_bytes(w(2, T=True), True) == rk2 + 8.0
+    assert bench.stage_bytes(w(2, force=True), False) == rk2 + 24.0
+    # species (SSP-RK3): read rho X^(s), rho, 3 face mass fluxes and, in two
+    # of three stages, rho X^n; write rho X
+    ns = 12
+    assert bench.species_bytes(ns) == pytest.approx(8 * ns + 8 + 24 + (2 / 3) * 8 * ns + 8 * ns)
+    assert bench.species_bytes(ns) == pytest.approx(288.0)
+    # RKL2 stage: 7 doubles read, 3 (internal-energy form) or 2 (T form) written
+    assert bench.BYTES_RKL2_STAGE == {0: 7 * 8.0 + 3 * 8.0, 1: 7 * 8.0 + 2 * 8.0}
