@@ -174,3 +174,91 @@ def test_pulse_converges_at_second_order(mode):
     assert 0.25e6 < runs[256].max() - 1e7 < 0.45e6
     e1, e2 = _l1(runs[128], runs[64]), _l1(runs[256], runs[128])
     assert 1.8 < math.log2(e1 / e2) < 2.6, (e1, e2)
+
+
+def _checkerboard_growth(p, rho0, s, frac, mode=orc.DIFF_TEMP):
+    """Amplification of the highest Fourier mode (+-1 alternating on every
+    axis with more than one cell) by one RKL2 step of s stages over
+    dt = frac (s^2 + s - 2)/4 dt_p, dt_p from the oracle.  Constant K
+    (chi = 1), temperature amplitude 1e-7: the operator is linear there."""
+    nz, ny, nx = p["nz"], p["ny"], p["nx"]
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sgn = np.ones((nz, ny, nx))
+    for idx, n in ((i, nx), (j, ny), (k, nz)):
+        if n > 1:
+            sgn = sgn * (1.0 - 2.0 * (idx % 2))
+    T0, amp = 3e6, 1e-7
+    T = T0 * (1.0 + amp * sgn)
+    rho = np.full((nz, ny, nx), rho0)
+    st = _state(p, rho, T)
+    op = _constant_k_opacity(p)
+    o = orc.Oracle(p)
+    dtp = o.parabolic_dt(rho, T, op)
+    dt = frac * (s * s + s - 2.0) / 4.0 * dtp
+    o.diffuse(st, dt, s, op, mode=mode)
+    dT = st["T"] - T0
+    return float(np.sum(dT * sgn) / np.sum(T0 * amp * sgn * sgn)), dtp
+
+
+@pytest.mark.parametrize("s", [4, 6])
+@pytest.mark.parametrize("dims", [(8, 6, 4, (1.0, 0.7, 2.3)), (10, 4, 1, (0.5, 1.9, 0.05))])
+def test_parabolic_limit_is_the_stability_edge_of_the_operator(s, dims):
+    """Delta t_p (Sect. 2.10, the parabolic CFL limit) pinned by what it
+    claims: with s stages the super step (s^2 + s - 2)/4 Delta t_p is the
+    edge of stability of the discrete operator.  The highest mode has the
+    eigenvalue -4 D sum_s 1/dx_s^2 (D = K/(rho c_v), the diffusivity of
+    rho c_v dT/dt = div K grad T), and for even s the RKL2 polynomial is 1
+    at the edge and grows beyond it: 1 % short of the step the mode decays,
+    1 % past it the mode grows.  A dropped 1/2, rho in place of rho^2 (here
+    rho = 3), a lost c_v or a wrong cell width (unequal on the three axes,
+    one axis of a single cell left out) moves the edge by a factor of 1.3
+    or more and fails one side."""
+    nx, ny, nz, L = dims
+    p = wl.gasrad_params(nx, ny, nz, hi=L)
+    below, dtp = _checkerboard_growth(p, 3.0, s, 0.99)
+    above, _ = _checkerboard_growth(p, 3.0, s, 1.01)
+    assert abs(below) < 1.0, (below, dtp)
+    assert above > 1.0, (above, dtp)
+    # and the amplification is R_s(z) at the edge's z for the eigenvalue of
+    # the highest mode, with D from the closed form above
+    rmu = p["rgas"] / p["mu"]
+    T0, rho0 = 3e6, 3.0
+    cv = rmu / (p["gamma"] - 1.0) + 4.0 * p["arad"] * T0 ** 3 / rho0
+    D = 4.0 * p["arad"] * orc.C_LIGHT_CODE / 3.0 / (rho0 * cv)
+    lam = -4.0 * D * sum(1.0 / (L[a] / n) ** 2 for a, n in enumerate((nx, ny, nz)) if n > 1)
+    for frac, got in ((0.99, below), (1.01, above)):
+        dt = frac * (s * s + s - 2.0) / 4.0 * dtp
+        assert got == pytest.approx(rkl2_poly(s, lam * dt), abs=2e-5), (frac, got)
+
+
+def _fewest_stages(r):
+    """Smallest s >= 2 whose stable super step (s^2 + s - 2)/4 Delta t_p
+    (Sect. 2.10) exceeds r Delta t_p, by counting up."""
+    s = 2
+    while (s * s + s - 2) / 4.0 <= r:
+        s += 1
+    return s
+
+
+def test_stage_count_is_the_fewest_stable_stages():
+    """N_STS (Sect. 2.10) pinned against the super-step length it comes
+    from: the fewest stages whose stable super step is longer than the
+    hyperbolic step, but never fewer than three.  Ratios on both sides of
+    every jump from 3 to 12 stages (the jump sits where (s^2 + s - 2)/4 is
+    reached exactly, which the formula counts to the next s), and the
+    minimum-of-three branch."""
+    edges = [(s * s + s - 2) / 4.0 for s in range(2, 13)]
+    ratios = [1e-3, 0.3, 0.999, 1.0, 1.001, 2.0]
+    for e in edges:
+        ratios += [e * (1 - 1e-9), e, e * (1 + 1e-9)]
+    for r in ratios:
+        dtp = 2.0 ** -10  # r dtp / dtp is exactly r
+        want = max(_fewest_stages(r), 3)
+        assert orc.rkl2_nsts(r * dtp, dtp) == want, (r, want)
+    # hand-worked cases: the step of exactly 4.5 Delta t_p is the edge of
+    # s = 4 and needs 5 stages; 4.49 needs 4; 0.5 takes the minimum 3
+    assert orc.rkl2_nsts(4.5, 1.0) == 5
+    assert orc.rkl2_nsts(4.49, 1.0) == 4
+    assert orc.rkl2_nsts(0.5, 1.0) == 3
+    assert orc.rkl2_nsts(2.5, 1.0) == 4
+    assert orc.rkl2_nsts(2.4, 1.0) == 3
