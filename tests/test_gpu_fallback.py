@@ -1,0 +1,125 @@
+"""The bracketed fallback of the EOS inversion inside the stage kernel.
+
+Sect. 2.2 inverts T(rho, e_int) by Newton from a guess; the plain solver
+behind it here (a safeguarded Newton-bisection on a closed-form bracket)
+takes over when the guess is not a positive finite number or when the
+Newton cap is reached.  These tests drive the stage into that branch on the
+GPU and compare the step with the oracle under the same cap and the same
+guesses:
+
+* the Newton cap lowered to one step, with the previous-step temperature
+  and with the learned guess, in FP64 and in the precision split: every
+  cell whose guess is not already converged falls back;
+* a previous-step temperature array holding NaN, zero and negative values
+  in some cells: exactly those cells fall back in the first stage.
+
+Tolerances as in the other parity tests: rel L2 1e-9 per field (FP64; the
+two sides stop the inversion within the 1e-11 tolerance, not bit for bit)
+and 1e-5 (split)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from paper_2604_12672_amd import eos_mlp
+from paper_2604_12672_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mhd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_12672_amd import mhd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2604_12672_amd import build
+        build.build()
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def model():
+    return eos_mlp.MLPGuess.load()
+
+
+def rel_l2(a, b):
+    den = math.sqrt(float(np.sum(b * b)))
+    return math.sqrt(float(np.sum((a - b) ** 2))) / den if den > 0 else math.sqrt(float(np.sum(a * a)))
+
+
+def check_state(out, ref, tol):
+    for k in ("Bx", "By", "Bz"):
+        assert rel_l2(out[k], ref[k]) <= tol, k
+    for f in range(5):
+        assert rel_l2(out["U"][f], ref["U"][f]) <= tol, f
+
+
+@pytest.mark.parametrize("learned", [False, True])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_newton_cap_of_one_falls_back(mhd, model, learned, precision, tol):
+    w = wl.smooth_box(18, 15, 12, eos=wl.EOS_GASRAD, bcz=1)
+    p = dict(w.params, newton_maxit=1)
+    print(f"case newton cap 1 learned={learned} prec={precision}", flush=True)
+    o = orc.Oracle(p, **w.extras())
+    ref = w.state()
+    dts = []
+    for _ in range(2):
+        dt = o.compute_dt(ref, w.cfl)
+        o.step(ref, dt)
+        dts.append(dt)
+    guess = mhd.GUESS_MLP if learned else mhd.GUESS_PREV_T
+    with mhd.Grid(p, precision=precision, eos_guess=guess) as g:
+        g.load(w, mlp=model if learned else None)
+        for dt in dts:
+            g.step(dt)
+        out = g.get_state(with_T=True)
+        diag = g.diagnostics()
+    check_state(out, ref, tol)
+    _, Tfin = o.primitives(ref)
+    np.testing.assert_allclose(out["T"], Tfin, rtol=1e-9 if precision == 0 else 1e-5)
+    n = w.ncells
+    print(f"fallbacks in the last step: {diag['fallbacks']} of {2 * n} cell-stages, "
+          f"Newton steps {diag['newton_iters']}, max {diag['newton_max']}", flush=True)
+    assert diag["fallbacks"] > 0
+    assert diag["newton_max"] <= 1
+    assert diag["error_flags"] == 0
+    # the learned guess is never converged before a step: every cell-stage
+    # falls back under a cap of one
+    if learned:
+        assert diag["fallbacks"] == 2 * n
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_bad_previous_temperatures_take_the_bracket(mhd, precision, tol):
+    w = wl.smooth_box(18, 15, 12, eos=wl.EOS_GASRAD, bcz=1)
+    print(f"case bad previous T prec={precision}", flush=True)
+    rng = np.random.default_rng(41)
+    T = w.T.copy()
+    idx = rng.choice(T.size, 60, replace=False)
+    T.flat[idx[:20]] = np.nan
+    T.flat[idx[20:40]] = 0.0
+    T.flat[idx[40:]] = -T.flat[idx[40:]]
+    dt = orc.Oracle(w.params, **w.extras()).compute_dt(w.state(), w.cfl)
+    o = orc.Oracle(w.params, **w.extras())
+    ref = w.state()
+    ref["T"] = T.copy()
+    o.step(ref, dt)
+    with mhd.Grid(w.params, precision=precision) as g:
+        g.load(w)
+        g.set_state(w.U, w.Bx, w.By, w.Bz, T=T)
+        g.step(dt)
+        out = g.get_state(with_T=True)
+        diag = g.diagnostics()
+    check_state(out, ref, tol)
+    _, Tfin = o.primitives(ref)
+    np.testing.assert_allclose(out["T"], Tfin, rtol=1e-9 if precision == 0 else 1e-5)
+    # the first stage starts from the exact temperature everywhere else
+    # (converged before any update) and from the bad guess in the 60 cells;
+    # the second stage starts from the first stage's solution
+    assert diag["fallbacks"] == 60, diag
+    assert diag["error_flags"] == 0

@@ -294,3 +294,51 @@ def test_split_vs_fp64_512_50_steps(mhd):
     print("split vs fp64 after 50 steps:", errs, flush=True)
     assert all(v <= 1e-5 for v in errs.values()), errs
     assert d32["divb_max"] < 1e-12
+
+
+_ORACLE_128 = {}
+
+
+def _oracle_128_50():
+    """The oracle on the stratified box with heating and cooling at 128^3,
+    50 steps of its own CFL sequence (about 20 s on 16 host cores)."""
+    if not _ORACLE_128:
+        w = wl.config(2, n=128)
+        o = orc.Oracle(w.params, **w.extras())
+        st = w.state()
+        dts = []
+        for _ in range(50):
+            dt = o.compute_dt(st, w.cfl)
+            o.step(st, dt)
+            dts.append(dt)
+        _ORACLE_128.update(w=w, ref=st, dts=dts)
+    return _ORACLE_128["w"], _ORACLE_128["ref"], _ORACLE_128["dts"]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_split_vs_oracle_128_50_steps(mhd, precision):
+    """The target's error report against the FP64 oracle itself: the
+    stratified box with heating and cooling (config 2's workload at 128^3,
+    where the oracle finishes in seconds), 50 steps on the oracle's dt
+    sequence.  Split precision: every field within rel L2 1e-5 of the
+    oracle, no floor; FP64: 1e-10 per field (momentum adds the oracle's own
+    rounding floor, as everywhere).  div B at round-off from the diagnostics
+    (whose parity with the oracle test_gpu_diagnostics checks)."""
+    print(f"case stratified 128^3 heating, 50 steps vs oracle, precision={precision}", flush=True)
+    w, ref, dts = _oracle_128_50()
+    out, diag, _ = gpu_run(mhd, w, 50, precision, dts=dts)
+    fo, fr = fields(out), fields(ref)
+    errs = {k: rel_l2(fo[k], fr[k]) for k in FIELDS}
+    print(f"precision={precision} rel L2 vs oracle after 50 steps:",
+          {k: f"{v:.2e}" for k, v in errs.items()}, f"divB {diag['divb_max']:.2e}", flush=True)
+    assert diag["divb_max"] < 1e-12
+    if precision == 1:
+        assert all(v <= 1e-5 for v in errs.values()), errs
+        return
+    floor = momentum_floor(w, dts) * math.sqrt(w.ncells)
+    for k, v in errs.items():
+        if k.startswith("m_"):
+            num = v * math.sqrt(float(np.sum(fr[k] ** 2)))
+            assert num <= 1e-10 * math.sqrt(float(np.sum(fr[k] ** 2))) + floor, (k, v, floor)
+        else:
+            assert v <= 1e-10, (k, v)
