@@ -152,10 +152,11 @@ int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *force,
    (log10 e_int - norm[2]) norm[3]) clipped to [-1, 1] and the guess
    T0 = 10^(y / norm[5] + norm[4]).  Host arrays: w1 [64][2] and b1 [64]
    FP32, w2 [64 out][64 in] and w3 [64] BF16 bit patterns, b2 [64] FP32, b3,
-   norm [6].  All three layers run on the matrix cores with FP32
-   accumulation, in a guess kernel that fills the context's guess array from
-   the stage input before each stage; the stage then polishes in FP64
-   Newton (at most 8 steps, then the bracketed solve).  Must precede the
+   norm [6].  Layers 1 and 2 run on the matrix cores (BF16 operands, FP32
+   accumulation), layer 3 as BF16 dot products on the vector unit, in a
+   guess kernel that fills the context's guess array from the stage input
+   before each stage; the stage then polishes in FP64 Newton (at most 8
+   steps, then the bracketed solve).  Must precede the
    first step.  Copies the weights. */
 int mhd_set_eos_mlp(mhd_ctx *ctx, const float *w1, const float *b1,
                     const uint16_t *w2, const float *b2, const uint16_t *w3,
