@@ -250,8 +250,44 @@ int mhd_parabolic_dt(mhd_ctx *ctx, double *dtp_out);
 int mhd_diffuse(mhd_ctx *ctx, double dt, int32_t nsts, int32_t mode,
                 int32_t *nsts_used);
 
-/* Message of the last failed call on this context ("" if none); a message
-   for a failed mhd_init_grid is returned for ctx == NULL. */
+/* ---- allocation-free CFL step ---- */
+
+/* Device scratch of mhd_compute_dt_noalloc per device (bytes). */
+#define MHD_NOALLOC_SCRATCH_BYTES ((2048 + 64) * 8)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the CFL
+   step of mhd_compute_dt, dt = cfl / max_cells sum_s (|v_s| + c_f,s)/dx_s
+   (eq. cfl, axes with one cell left out), of a state held in the caller's
+   device memory, without a context.
+     desc        grid and EOS as for mhd_init_grid (validated the same way);
+                 eos_guess must be MHD_GUESS_PREV_T; the scheme options are
+                 not used
+     U, Bx, By, Bz  device arrays in the layout of mhd_set_state
+     T           device temperature guesses of the gas+radiation inversion,
+                 or NULL (bracketed solve); ignored for the ideal gas
+     dt_out      one device double, receives dt
+     flags_out   one device int32 (nullable), receives 0 or the error bits
+                 of mhd_diag.error_flags (1 non-physical, 2 EOS failure)
+     hip_stream  the stream to run on (NULL: the null stream)
+   Asynchronous on hip_stream; allocates nothing and never synchronises.
+   The per-block maxima and the error bits live in a fixed device array of
+   MHD_NOALLOC_SCRATCH_BYTES on each device, kept until the process ends and
+   shared by every call on that device: calls that overlap on one device
+   (on different streams or threads) race and must be serialised by the
+   caller.  Any grid the descriptor check accepts fits (the reduction
+   strides over cells beyond 2048 blocks of 256); larger grids
+   (nx ny (nz+1) >= 2^32) and invalid arguments return MHD_ERR_ARG, a
+   device other than gfx950 MHD_ERR_NO_DEVICE, a failed launch MHD_ERR_HIP,
+   with the message in mhd_last_error(NULL).  The result is bit for bit the
+   one mhd_compute_dt gives for the same state and guesses. */
+int mhd_compute_dt_noalloc(const mhd_grid_desc *desc, const double *U, const double *Bx,
+                           const double *By, const double *Bz, const double *T, double cfl,
+                           double *dt_out, int32_t *flags_out, void *hip_stream);
+
+/* Message of the last failed call on this context ("" if none); for
+   ctx == NULL, the message of the last failed mhd_init_grid or
+   mhd_compute_dt_noalloc on this thread. */
 const char *mhd_last_error(const mhd_ctx *ctx);
 
 /* Free the context and its device buffers (NULL is a no-op). */

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhd.so")
 SOURCES = ["mhd_api.hip", "mhd_kernels.hip", "mhd_diffusion.hip", "mhd_flatten.hip",
-           "mhd_species.hip", "mhd_mathcheck.hip"]
+           "mhd_species.hip", "mhd_mathcheck.hip", "mhd_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

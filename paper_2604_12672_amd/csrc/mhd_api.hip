@@ -161,6 +161,48 @@ int latched(mhd_ctx *h) {
 }  // namespace
 
 namespace mhd {
+// grid and physics constants of the kernels from a validated descriptor
+void fill_phys(const mhd_grid_desc *desc, Phys &ph) {
+  ph.nx = desc->nx;
+  ph.ny = desc->ny;
+  ph.nz = desc->nz;
+  ph.reflect = desc->bc[2] == MHD_BC_REFLECT;
+  ph.nzf = ph.reflect ? desc->nz + 1 : desc->nz;
+  ph.gasrad = desc->eos == MHD_EOS_GASRAD;
+  ph.dx = (desc->hi[0] - desc->lo[0]) / desc->nx;
+  ph.dy = (desc->hi[1] - desc->lo[1]) / desc->ny;
+  ph.dz = (desc->hi[2] - desc->lo[2]) / desc->nz;
+  ph.idx = 1.0 / ph.dx;
+  ph.idy = 1.0 / ph.dy;
+  ph.idz = 1.0 / ph.dz;
+  ph.gamma = desc->gamma;
+  ph.gm1 = desc->gamma - 1.0;
+  ph.igm1 = 1.0 / (desc->gamma - 1.0);
+  ph.rmu = ph.gasrad ? desc->rgas / desc->mu : 0.0;
+  ph.arad = ph.gasrad ? desc->arad : 0.0;
+  ph.cg = ph.gasrad ? desc->rgas / ((desc->gamma - 1.0) * desc->mu) : 0.0;
+  ph.icg = ph.cg > 0.0 ? 1.0 / ph.cg : 0.0;
+  ph.gz = desc->grav[2];
+  ph.newton_tol = desc->newton_tol;
+  ph.newton_maxit = desc->newton_maxit;
+  ph.xi_mode = desc->xi_mode;
+  ph.recon = desc->recon;
+  ph.mach_cut = desc->mach_cut;
+  ph.imach_cut = desc->mach_cut > 0.0 ? 1.0 / desc->mach_cut : 0.0;
+  ph.dims_active[0] = desc->nx > 1;
+  ph.dims_active[1] = desc->ny > 1;
+  ph.dims_active[2] = desc->nz > 1;
+  // after the learned guess Newton gets 8 steps before the bracketed solve
+  ph.newton_maxit_mlp = desc->newton_maxit < 8 ? desc->newton_maxit : 8;
+}
+
+int validate_desc(const mhd_grid_desc *desc, std::string &msg) { return check_desc(desc, msg); }
+
+// message of a failed call without a context (mhd_last_error(NULL))
+void set_context_free_error(const std::string &msg) { g_init_err = msg; }
+}  // namespace mhd
+
+namespace mhd {
 // accuracy check of the device reciprocal / square root (mhd_mathcheck.hip)
 hipError_t launch_math_check(hipStream_t s, const double *x, double *out, long long n);
 }  // namespace mhd
@@ -196,37 +238,7 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
   c.device = dev;
   c.stream = (hipStream_t)hip_stream;
   mhd::Phys &ph = c.ph;
-  ph.nx = desc->nx;
-  ph.ny = desc->ny;
-  ph.nz = desc->nz;
-  ph.reflect = desc->bc[2] == MHD_BC_REFLECT;
-  ph.nzf = ph.reflect ? desc->nz + 1 : desc->nz;
-  ph.gasrad = desc->eos == MHD_EOS_GASRAD;
-  ph.dx = (desc->hi[0] - desc->lo[0]) / desc->nx;
-  ph.dy = (desc->hi[1] - desc->lo[1]) / desc->ny;
-  ph.dz = (desc->hi[2] - desc->lo[2]) / desc->nz;
-  ph.idx = 1.0 / ph.dx;
-  ph.idy = 1.0 / ph.dy;
-  ph.idz = 1.0 / ph.dz;
-  ph.gamma = desc->gamma;
-  ph.gm1 = desc->gamma - 1.0;
-  ph.igm1 = 1.0 / (desc->gamma - 1.0);
-  ph.rmu = ph.gasrad ? desc->rgas / desc->mu : 0.0;
-  ph.arad = ph.gasrad ? desc->arad : 0.0;
-  ph.cg = ph.gasrad ? desc->rgas / ((desc->gamma - 1.0) * desc->mu) : 0.0;
-  ph.icg = ph.cg > 0.0 ? 1.0 / ph.cg : 0.0;
-  ph.gz = desc->grav[2];
-  ph.newton_tol = desc->newton_tol;
-  ph.newton_maxit = desc->newton_maxit;
-  ph.xi_mode = desc->xi_mode;
-  ph.recon = desc->recon;
-  ph.mach_cut = desc->mach_cut;
-  ph.imach_cut = desc->mach_cut > 0.0 ? 1.0 / desc->mach_cut : 0.0;
-  ph.dims_active[0] = desc->nx > 1;
-  ph.dims_active[1] = desc->ny > 1;
-  ph.dims_active[2] = desc->nz > 1;
-  // after the learned guess Newton gets 8 steps before the bracketed solve
-  ph.newton_maxit_mlp = desc->newton_maxit < 8 ? desc->newton_maxit : 8;
+  mhd::fill_phys(desc, ph);
   c.ncell = (size_t)desc->nx * desc->ny * desc->nz;
   c.nfz = (size_t)desc->nx * desc->ny * ph.nzf;
   // z planes per stage block: a longer segment re-reads fewer halo planes
@@ -268,6 +280,9 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out) {
     return MHD_ERR_HIP;
   };
   hipError_t e;
+  // the allocation-free entry point's scratch address on this device
+  if ((e = mhd::noalloc_setup(dev)) != hipSuccess)
+    return cleanup(e, "hipGetSymbolAddress scratch");
   for (int s = 0; s < 3; ++s) {
     if ((e = hipMalloc(&c.U[s], sizeof(double) * 5 * c.ncell)) != hipSuccess)
       return cleanup(e, "hipMalloc U");

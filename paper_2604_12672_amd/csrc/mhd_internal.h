@@ -132,6 +132,25 @@ hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz,
                                const double *T, double cfl, double *dt_dev,
                                double *Tout = nullptr, double *Pout = nullptr);
+// most blocks of the CFL reduction (grid-stride beyond that)
+constexpr int CFL_MAX_BLOCKS = 2048;
+// the CFL kernels on explicit buffers: per-block partial maxima in
+// partial[0 .. cfl_partial_blocks(n)), the largest signal speed into
+// smax_out, cfl / smax into dt_dev, error bits ORed into flags; mlp is the
+// packed guess network (learned mode only, else NULL)
+int cfl_partial_blocks(size_t ncell);
+hipError_t launch_signal_speed_raw(const Phys &ph, hipStream_t stream, bool learned,
+                                   const double *U, const double *Bx, const double *By,
+                                   const double *Bz, const double *T, const void *mlp,
+                                   double *partial, int *flags, double cfl, double *dt_dev,
+                                   double *smax_out, double *Tout, double *Pout);
+// descriptor checks and kernel constants shared by every entry point
+int validate_desc(const mhd_grid_desc *desc, std::string &msg);
+void fill_phys(const mhd_grid_desc *desc, Phys &ph);
+void set_context_free_error(const std::string &msg);
+// device address of the allocation-free entry point's scratch array on
+// device dev (the current device), resolved once (mhd_noalloc.hip)
+hipError_t noalloc_setup(int dev);
 hipError_t launch_init_temperature(const Ctx &c, const double *U,
                                    const double *Bx, const double *By,
                                    const double *Bz, const double *Tg, double *T);

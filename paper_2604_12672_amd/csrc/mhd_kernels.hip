@@ -748,7 +748,7 @@ hipError_t launch_stage(const Ctx &c, const StagePtrs &p, double a, double b,
 // ---------------------------------------------------------------------------
 
 constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 2048;
+constexpr int RED_BLOCKS = CFL_MAX_BLOCKS;
 
 template <bool GR, bool ML>
 __global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
@@ -848,25 +848,38 @@ __global__ void finish_dt_kernel(const double *__restrict__ partial, int nb,
   }
 }
 
+int cfl_partial_blocks(size_t ncell) {
+  const size_t nb = (ncell + RED_THREADS - 1) / RED_THREADS;
+  return (int)(nb < (size_t)RED_BLOCKS ? nb : (size_t)RED_BLOCKS);
+}
+
+hipError_t launch_signal_speed_raw(const Phys &ph, hipStream_t stream, bool learned,
+                                   const double *U, const double *Bx, const double *By,
+                                   const double *Bz, const double *T, const void *mlp,
+                                   double *partial, int *flags, double cfl, double *dt_dev,
+                                   double *smax_out, double *Tout, double *Pout) {
+  const int nb = cfl_partial_blocks((size_t)ph.nx * ph.ny * ph.nz);
+  if (!ph.gasrad)
+    hipLaunchKernelGGL((signal_speed_kernel<false, false>), dim3(nb), dim3(RED_THREADS), 0,
+                       stream, ph, U, Bx, By, Bz, T, mlp, partial, flags, nullptr, Pout);
+  else if (learned)
+    hipLaunchKernelGGL((signal_speed_kernel<true, true>), dim3(nb), dim3(RED_THREADS), 0,
+                       stream, ph, U, Bx, By, Bz, T, mlp, partial, flags, Tout, Pout);
+  else
+    hipLaunchKernelGGL((signal_speed_kernel<true, false>), dim3(nb), dim3(RED_THREADS), 0,
+                       stream, ph, U, Bx, By, Bz, T, mlp, partial, flags, Tout, Pout);
+  hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(RED_THREADS), 0, stream, partial, nb, cfl,
+                     dt_dev, smax_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_signal_speed(const Ctx &c, const double *U, const double *Bx,
                                const double *By, const double *Bz,
                                const double *T, double cfl, double *dt_dev, double *Tout,
                                double *Pout) {
-  const size_t n = c.ncell;
-  int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
-  nb = nb < RED_BLOCKS ? nb : RED_BLOCKS;
-  if (!c.ph.gasrad)
-    hipLaunchKernelGGL((signal_speed_kernel<false, false>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, nullptr, Pout);
-  else if (c.d.eos_guess == MHD_GUESS_MLP)
-    hipLaunchKernelGGL((signal_speed_kernel<true, true>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, Tout, Pout);
-  else
-    hipLaunchKernelGGL((signal_speed_kernel<true, false>), dim3(nb), dim3(RED_THREADS), 0,
-                       c.stream, c.ph, U, Bx, By, Bz, T, c.mlp, c.red, c.flags, Tout, Pout);
-  hipLaunchKernelGGL(finish_dt_kernel, dim3(1), dim3(RED_THREADS), 0, c.stream, c.red, nb, cfl,
-                     dt_dev, c.red + RED_BLOCKS);
-  return hipGetLastError();
+  return launch_signal_speed_raw(c.ph, c.stream, c.d.eos_guess == MHD_GUESS_MLP, U, Bx, By, Bz,
+                                 T, c.mlp, c.red, c.flags, cfl, dt_dev, c.red + RED_BLOCKS, Tout,
+                                 Pout);
 }
 
 // ---------------------------------------------------------------------------

@@ -61,7 +61,7 @@ EXPORTS = ["mhd_init_grid", "mhd_set_background", "mhd_set_sources", "mhd_set_eo
            "mhd_get_state", "mhd_sync", "mhd_diagnostics", "mhd_last_error", "mhd_destroy",
            "mhd_shock_flags", "mhd_set_species", "mhd_get_species",
            "mhd_launch_info", "mhd_set_opacity", "mhd_parabolic_dt", "mhd_diffuse",
-           "mhd_math_check"]
+           "mhd_math_check", "mhd_compute_dt_noalloc"]
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load():
     L.mhd_set_opacity.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
     L.mhd_parabolic_dt.argtypes = [vp, C.POINTER(C.c_double)]
     L.mhd_diffuse.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.mhd_compute_dt_noalloc.argtypes = [C.POINTER(GridDesc), vp, vp, vp, vp, vp, C.c_double,
+                                         vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = C.c_int if name != "mhd_last_error" else C.c_char_p
     _lib = L
@@ -182,6 +184,36 @@ def math_check(x):
     if rc != 0:
         raise MHDError(rc, "mhd_math_check failed")
     return out
+
+
+def compute_dt_noalloc(params: dict, U, Bx, By, Bz, T, cfl, dt_out, flags_out=None,
+                       stream=None):
+    """CFL step of a state held in CUDA float64 tensors, without a context
+    and without allocating: dt into dt_out (a one-element CUDA float64
+    tensor) and the error bits into flags_out (a one-element CUDA int32
+    tensor, optional), asynchronously on `stream` (default: torch's current
+    stream)."""
+    import torch
+    L = load()
+    d = make_desc(params)
+    assert dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1
+    if flags_out is not None:
+        assert flags_out.is_cuda and flags_out.dtype == torch.int32 and flags_out.numel() >= 1
+    nz, ny, nx = d.nz, d.ny, d.nx
+    nzf = nz + 1 if d.bc[2] == BC_REFLECT else nz
+    assert tuple(U.shape) == (5, nz, ny, nx) and tuple(Bx.shape) == (nz, ny, nx)
+    assert tuple(By.shape) == (nz, ny, nx) and tuple(Bz.shape) == (nzf, ny, nx)
+    if T is not None:
+        assert tuple(T.shape) == (nz, ny, nx)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    rc = L.mhd_compute_dt_noalloc(C.byref(d), _ptr(U, DEVICE), _ptr(Bx, DEVICE),
+                                  _ptr(By, DEVICE), _ptr(Bz, DEVICE), _ptr(T, DEVICE),
+                                  float(cfl), C.c_void_p(dt_out.data_ptr()),
+                                  None if flags_out is None else C.c_void_p(flags_out.data_ptr()),
+                                  C.c_void_p(stream))
+    if rc != 0:
+        raise MHDError(rc, L.mhd_last_error(None).decode())
 
 
 class Grid:
