@@ -153,11 +153,10 @@ def stage_bytes(w, learned):
 def extra_bytes(w, learned):
     """Bytes per zone and stage the stage kernel moves beyond the
     algorithmic ones: the learned guess it reads (the guess kernel's
-    output), and a forcing field read from HBM."""
-    b = BYTES_GUESS_ARRAY if (learned and w.T is not None) else 0.0
-    if w.force is not None:
-        b += 24.0
-    return b
+    output).  Forcing modes cost 120 B per column and launch (the
+    coefficients of the column), under 4 B per zone at 37 planes per
+    column segment, and are left out."""
+    return BYTES_GUESS_ARRAY if (learned and w.T is not None) else 0.0
 
 
 def roofline(w, stage_ms, path, learned=False):

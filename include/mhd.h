@@ -138,12 +138,26 @@ int mhd_init_grid(const mhd_grid_desc *desc, void *hip_stream, mhd_ctx **out);
    call the background is zero (the full state is reconstructed). */
 int mhd_set_background(mhd_ctx *ctx, const double *w_cc, const double *w_fz);
 
-/* Energy source per unit volume heat [nz] (host, nullable) and acceleration
-   field force [3][nz][ny][nx] (`where`, nullable; adds rho f to the momentum
-   and m.f to the energy equation).  Neither is part of the equilibrium
-   source S_hat. */
-int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *force,
-                    int32_t where);
+/* Most forcing modes of mhd_set_sources. */
+#define MHD_MAX_FMODES 4096
+
+/* Energy source per unit volume heat [nz] (host, nullable; the heating and
+   cooling layers of the stratified box) and a forcing acceleration given by
+   Fourier modes (host, fmodes [nmodes][7], nullable with nmodes = 0; the
+   driven-turbulence setup), adding rho f to the momentum and m.f to the
+   energy equation (Sect. 2.1 sources); neither is part of the equilibrium
+   source S_hat (Sect. 2.8).  Mode m = (k_x, k_y, k_z, a_x, a_y, a_z, phi)
+   contributes a cos(2 pi (k_x X + k_y Y + k_z Z) + phi) with
+   X = (x - lo[0]) / (hi[0] - lo[0]) (likewise Y, Z) at the cell centre;
+   wavenumbers are integers with |k_x|, |k_y| <= 4096 and |k_z| <= 2, at
+   most MHD_MAX_FMODES modes (else MHD_ERR_ARG).  The library sums the
+   modes once into per-column coefficients of the z basis {1, cos 2piZ,
+   sin 2piZ, cos 4piZ, sin 4piZ} (120 B per column) and the stage kernel
+   evaluates the forcing of every cell from them (in FP64; the split path
+   keeps the coefficients in FP32, 6e-8 of the forcing).  A call replaces
+   both sources; synchronises. */
+int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *fmodes,
+                    int32_t nmodes);
 
 /* Learned initial guess of the Newton temperature inversion (contexts
    created with MHD_GUESS_MLP; not part of the paper's method).  Network

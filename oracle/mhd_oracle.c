@@ -1197,6 +1197,33 @@ int orc_compute_dt(const orc_cfg *c, const double *U, const double *Bx,
 /* Diagnostics                                                          */
 /* ------------------------------------------------------------------ */
 
+void orc_forcing(const orc_cfg *c, const double *modes, int nmodes, const double origin[3],
+                 const double period[3], double *out) {
+  const size_t n = (size_t)c->nx * c->ny * c->nz;
+  const double pi2 = 6.283185307179586476925286766559;
+#pragma omp parallel for collapse(3) schedule(static)
+  for (int k = 0; k < c->nz; ++k)
+    for (int j = 0; j < c->ny; ++j)
+      for (int i = 0; i < c->nx; ++i) {
+        const double X = (origin[0] + (i + 0.5) * c->dx) / period[0];
+        const double Y = (origin[1] + (j + 0.5) * c->dy) / period[1];
+        const double Z = (origin[2] + (k + 0.5) * c->dz) / period[2];
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int m = 0; m < nmodes; ++m) {
+          const double *md = modes + 7 * m;
+          const double ph = pi2 * (md[0] * X + md[1] * Y + md[2] * Z) + md[6];
+          const double cs = cos(ph);
+          f[0] += md[3] * cs;
+          f[1] += md[4] * cs;
+          f[2] += md[5] * cs;
+        }
+        const size_t q = ((size_t)k * c->ny + j) * c->nx + i;
+        out[q] = f[0];
+        out[n + q] = f[1];
+        out[2 * n + q] = f[2];
+      }
+}
+
 void orc_divb(const orc_cfg *c, const double *Bx, const double *By,
               const double *Bz, double *out) {
   grid_t g;

@@ -70,6 +70,17 @@ typedef struct {
   const double *force;   /* [3][nz][ny][nx] acceleration field, or NULL     */
 } orc_cfg;
 
+/* Forcing acceleration from Fourier modes (the driven-turbulence setup;
+   not a step of the paper's scheme): at every cell centre x,
+     f(x) = sum_m a_m cos(2 pi (k_m,x X + k_m,y Y + k_m,z Z) + phi_m),
+   X = (origin[0] + (i + 1/2) dx) / period[0], likewise Y, Z, evaluated term
+   by term.  modes [nmodes][7] = (k_x, k_y, k_z, a_x, a_y, a_z, phi) with
+   integer wavenumbers; origin = position of the grid's first cell corner
+   relative to the forcing's reference corner; period = the forcing's box
+   lengths.  out [3][nz][ny][nx]. */
+void orc_forcing(const orc_cfg *c, const double *modes, int nmodes, const double origin[3],
+                 const double period[3], double *out);
+
 /* Forward EOS at (rho, T): pressure, specific internal energy, c_v and the
    adiabatic sound speed squared (Sect. 2.2, eqs. prad/erad). */
 int orc_eos_thermo(const orc_cfg *c, double rho, double T, double *P,

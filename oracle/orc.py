@@ -59,6 +59,8 @@ def lib():
         L.orc_residual.argtypes = [C.POINTER(_Cfg)] + [_DP] * 10
         L.orc_compute_dt.argtypes = [C.POINTER(_Cfg), _DP, _DP, _DP, _DP, _DP,
                                      C.c_double, _DP]
+        L.orc_forcing.argtypes = [C.POINTER(_Cfg), _DP, C.c_int, _DP, _DP, _DP]
+        L.orc_forcing.restype = None
         L.orc_divb.argtypes = [C.POINTER(_Cfg), _DP, _DP, _DP, _DP]
         L.orc_divb.restype = None
         L.orc_primitives.argtypes = [C.POINTER(_Cfg)] + [_DP] * 7
@@ -115,10 +117,17 @@ DEFAULTS = dict(
 
 class Oracle:
     """The oracle bound to one problem description (a dict of grid and
-    physics parameters, plus optional background, heating and forcing
-    arrays)."""
+    physics parameters, plus optional background and heating arrays, and a
+    forcing given as an acceleration field or as Fourier modes).
 
-    def __init__(self, params: dict, bg_cc=None, bg_fz=None, heat=None, force=None):
+    fmodes [nmodes][7] = (k_x, k_y, k_z, a_x, a_y, a_z, phi): the forcing
+    sum_m a_m cos(2 pi k_m . (x / L) + phi_m), evaluated at the cell centres
+    by orc_forcing; x is measured from the forcing's reference corner, which
+    lies at -forcing_origin from this grid's first cell corner (a window of a
+    larger grid passes its offset), L = forcing_period (default: this box)."""
+
+    def __init__(self, params: dict, bg_cc=None, bg_fz=None, heat=None, force=None,
+                 fmodes=None, forcing_origin=(0.0, 0.0, 0.0), forcing_period=None):
         p = dict(DEFAULTS)
         p.update(params)
         self.p = p
@@ -126,6 +135,10 @@ class Oracle:
         lo, hi = p.get("lo", (0.0, 0.0, 0.0)), p.get("hi", (1.0, 1.0, 1.0))
         self.shape = (nz, ny, nx)
         self.nzf = nz + 1 if p["bcz"] == BC_REFLECT else nz
+        if fmodes is not None:
+            assert force is None, "give the forcing as a field or as modes, not both"
+            period = forcing_period or tuple(hi[a] - lo[a] for a in range(3))
+            force = self.forcing_field(fmodes, forcing_origin, period)
         self._keep = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
                       for a in (bg_cc, bg_fz, heat, force)]
         bcc, bfz, ht, fc = self._keep
@@ -138,6 +151,19 @@ class Oracle:
             int(p["xi_mode"]), int(p["recon"]), int(p["flatten"]), float(p["eps_sf"]),
             int(p["nspecies"]), _ptr(bcc), _ptr(bfz), _ptr(ht), _ptr(fc),
         )
+
+    def forcing_field(self, fmodes, origin, period):
+        """[3][nz][ny][nx] acceleration of the Fourier modes (orc_forcing)."""
+        nx, ny, nz = int(self.p["nx"]), int(self.p["ny"]), int(self.p["nz"])
+        lo, hi = self.p.get("lo", (0.0, 0.0, 0.0)), self.p.get("hi", (1.0, 1.0, 1.0))
+        cfg = _Cfg(nx, ny, nz, (hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny,
+                   (hi[2] - lo[2]) / nz)
+        m = np.ascontiguousarray(fmodes, dtype=np.float64).reshape(-1, 7)
+        o = np.ascontiguousarray(origin, dtype=np.float64)
+        L = np.ascontiguousarray(period, dtype=np.float64)
+        out = np.empty((3, nz, ny, nx))
+        lib().orc_forcing(C.byref(cfg), _ptr(m), len(m), _ptr(o), _ptr(L), _ptr(out))
+        return out
 
     # -- state helpers -------------------------------------------------
     def _state(self, st):

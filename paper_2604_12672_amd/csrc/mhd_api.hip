@@ -357,7 +357,8 @@ int mhd_destroy(mhd_ctx *h) {
   (void)hipFree(c.bg_cc);
   (void)hipFree(c.bg_fz);
   (void)hipFree(c.heat);
-  (void)hipFree(c.force);
+  (void)hipFree(c.fcoef);
+  (void)hipFree(c.fzb);
   (void)hipFree(c.red);
   (void)hipFree(c.dt_dev);
   (void)hipFree(c.flags);
@@ -404,11 +405,23 @@ int mhd_set_background(mhd_ctx *h, const double *w_cc, const double *w_fz) {
   return MHD_OK;
 }
 
-int mhd_set_sources(mhd_ctx *h, const double *heat, const double *force, int32_t where) {
+int mhd_set_sources(mhd_ctx *h, const double *heat, const double *fmodes, int32_t nmodes) {
   if (!h) return MHD_ERR_ARG;
   mhd::Ctx &c = h->c;
-  if (where != MHD_HOST && where != MHD_DEVICE) return fail(h, MHD_ERR_ARG, "bad `where`");
+  if (nmodes < 0 || nmodes > MHD_MAX_FMODES || (nmodes > 0 && !fmodes))
+    return fail(h, MHD_ERR_ARG, "nmodes must be 0 .. MHD_MAX_FMODES with a mode array");
+  for (int m = 0; m < nmodes; ++m) {
+    const double *md = fmodes + 7 * m;
+    for (int a = 0; a < 3; ++a)
+      if (!(md[a] == std::floor(md[a]) && std::fabs(md[a]) <= (a == 2 ? 2.0 : 4096.0)))
+        return fail(h, MHD_ERR_ARG,
+                    "mode wavenumbers must be integers, |k_x|, |k_y| <= 4096, |k_z| <= 2");
+    for (int a = 3; a < 7; ++a)
+      if (!std::isfinite(md[a])) return fail(h, MHD_ERR_ARG, "mode amplitudes and phases must be finite");
+  }
   if (heat) {
+    for (int k = 0; k < c.ph.nz; ++k)
+      if (!std::isfinite(heat[k])) return fail(h, MHD_ERR_ARG, "heating must be finite");
     if (!c.heat) HIPCHK(h, hipMalloc(&c.heat, sizeof(double) * c.ph.nz));
     HIPCHK(h, hipMemcpyAsync(c.heat, heat, sizeof(double) * c.ph.nz, hipMemcpyHostToDevice, c.stream));
   } else if (c.heat) {
@@ -416,13 +429,57 @@ int mhd_set_sources(mhd_ctx *h, const double *heat, const double *force, int32_t
     (void)hipFree(c.heat);
     c.heat = nullptr;
   }
-  if (force) {
-    if (!c.force) HIPCHK(h, hipMalloc(&c.force, sizeof(double) * 3 * c.ncell));
-    HIPCHK(h, hipMemcpyAsync(c.force, force, sizeof(double) * 3 * c.ncell, kind_in(where), c.stream));
-  } else if (c.force) {
+  if (nmodes > 0) {
+    // f(x) = sum_m a_m cos(alpha_m(x, y) + 2 pi k_z,m Z), alpha_m = 2 pi
+    // (k_x X + k_y Y) + phi_m, X = (x - lo)/L at cell centres.  With
+    // cos(alpha + beta) = cos alpha cos beta - sin alpha sin beta, each
+    // column's forcing is a combination of the z basis {1, cos 2piZ,
+    // sin 2piZ, cos 4piZ, sin 4piZ}; its 15 coefficients (3 components x 5)
+    // are summed here once, the stage kernel evaluates the combination.
+    const int nx = c.ph.nx, ny = c.ph.ny, nz = c.ph.nz;
+    const double pi2 = 6.283185307179586476925286766559;
+    const size_t nxy = (size_t)nx * ny;
+    std::vector<double> coef((size_t)3 * mhd::FZB * nxy, 0.0), zb((size_t)mhd::FZB * nz);
+    for (int m = 0; m < nmodes; ++m) {
+      const double *md = fmodes + 7 * m;
+      const int kz = (int)md[2];
+      const int d = kz == 0 ? 0 : (kz == 1 || kz == -1 ? 1 : 3);
+      const double sg = kz < 0 ? -1.0 : 1.0;
+      for (int j = 0; j < ny; ++j) {
+        const double Y = (j + 0.5) / ny;
+        for (int i = 0; i < nx; ++i) {
+          const double X = (i + 0.5) / nx;
+          const double al = pi2 * (md[0] * X + md[1] * Y) + md[6];
+          const double ca = std::cos(al), sa = std::sin(al);
+          const size_t q = (size_t)j * nx + i;
+          for (int cc = 0; cc < 3; ++cc) {
+            double *cf = coef.data() + (size_t)(cc * mhd::FZB) * nxy + q;
+            cf[(size_t)d * nxy] += md[3 + cc] * ca;
+            if (kz != 0) cf[(size_t)(d + 1) * nxy] -= sg * md[3 + cc] * sa;
+          }
+        }
+      }
+    }
+    for (int k = 0; k < nz; ++k) {
+      const double Z = (k + 0.5) / nz;
+      zb[k] = 1.0;
+      zb[(size_t)nz + k] = std::cos(pi2 * Z);
+      zb[(size_t)2 * nz + k] = std::sin(pi2 * Z);
+      zb[(size_t)3 * nz + k] = std::cos(2.0 * pi2 * Z);
+      zb[(size_t)4 * nz + k] = std::sin(2.0 * pi2 * Z);
+    }
+    if (!c.fcoef) HIPCHK(h, hipMalloc(&c.fcoef, sizeof(double) * coef.size()));
+    if (!c.fzb) HIPCHK(h, hipMalloc(&c.fzb, sizeof(double) * zb.size()));
+    HIPCHK(h, hipMemcpyAsync(c.fcoef, coef.data(), sizeof(double) * coef.size(),
+                             hipMemcpyHostToDevice, c.stream));
+    HIPCHK(h, hipMemcpyAsync(c.fzb, zb.data(), sizeof(double) * zb.size(), hipMemcpyHostToDevice,
+                             c.stream));
+    HIPCHK(h, hipStreamSynchronize(c.stream));  // the host tables go out of scope
+  } else if (c.fcoef) {
     HIPCHK(h, hipStreamSynchronize(c.stream));
-    (void)hipFree(c.force);
-    c.force = nullptr;
+    (void)hipFree(c.fcoef);
+    (void)hipFree(c.fzb);
+    c.fcoef = c.fzb = nullptr;
   }
   HIPCHK(h, hipStreamSynchronize(c.stream));
   return MHD_OK;
@@ -551,7 +608,8 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     p.bg_cc = c.bg_cc;
     p.bg_fz = c.bg_fz;
     p.heat = c.heat;
-    p.force = c.force;
+    p.fcoef = c.fcoef;
+    p.fzb = c.fzb;
     p.dt_dev = dt_dev;
     p.flags = c.flags;
     p.newton_stats = c.nstats;

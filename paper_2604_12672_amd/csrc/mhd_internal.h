@@ -16,6 +16,8 @@ namespace mhd {
 constexpr int TT = 16;        // threads per tile edge
 constexpr int TB = TT - 2;    // output columns per tile edge
 constexpr int NTHREADS = TT * TT;
+// z basis of the forcing modes: wavenumbers |k_z| <= 2
+constexpr int FZB = 5;
 // Longest z segment of a stage block (the block stages the background
 // profile of its segment and halo in LDS).
 constexpr int ZSEG_MAX = 64;
@@ -49,7 +51,12 @@ struct StagePtrs {
   const double *Tin;                   // EOS guess (gas+radiation)
   double *Tout;                        // EOS solution (owned cells)
   const double *bg_cc, *bg_fz;         // [4][nz], [4][nzf]
-  const double *heat, *force;          // nullable
+  const double *heat;                  // nullable
+  // forcing from Fourier modes (nullable): per column the coefficients of
+  // the z basis {1, cos 2piZ, sin 2piZ, cos 4piZ, sin 4piZ} for each
+  // component, fcoef [3 * FZB][ny][nx], and that basis at the cell
+  // centres, fzb [FZB][nz]
+  const double *fcoef, *fzb;
   const double *dt_dev;                // device dt (nullable: use dt_host)
   int newton_cap;                      // Newton steps before the bracketed solve
   const uint8_t *flat = nullptr;       // shock-flattening flags [n] (nullable)
@@ -91,7 +98,8 @@ struct Ctx {
   double *T[2] = {nullptr, nullptr};
   int tcur = 0;
   double *bg_cc = nullptr, *bg_fz = nullptr;
-  double *heat = nullptr, *force = nullptr;
+  double *heat = nullptr;
+  double *fcoef = nullptr, *fzb = nullptr;  // forcing tables (see StagePtrs)
   double *dt_dev = nullptr;       // [1]
   void *mlp = nullptr;            // packed guess network on the device
   bool have_mlp = false;

@@ -234,7 +234,7 @@ __device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, i
   for (int i = tid; i < (int)(sizeof(MlpLds) / 16); i += nthreads) d4[i] = s4[i];
 }
 
-// XF: the optional features of a stage (forcing field, shock-flattening
+// XF: the optional features of a stage (forcing modes, shock-flattening
 // flags, species mass fluxes); the variant without them carries none of
 // their code, pointers or registers.
 template <typename R, bool GR, bool XF>
@@ -282,6 +282,13 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   // z faces z0 .. z1.  Uniform per plane, so every read is a broadcast.
   __shared__ double sBc[5][ZSEG_MAX + 4];  // rho, P, gamma_e, gamma_c, heat
   __shared__ double sBf[4][ZSEG_MAX + 1];
+  // forcing from Fourier modes: the z basis of the same planes, and this
+  // thread's column coefficients (3 components x FZB), as R
+  __shared__ double sZB[XF ? FZB : 1][ZSEG_MAX + 4];
+  __shared__ R sFC[XF ? 3 * FZB : 1][NTHREADS];
+  const size_t plane = (size_t)ph.nx * ph.ny;
+  const size_t ncell = plane * ph.nz;
+  const size_t colq = (size_t)gj * ph.nx + gi;
   {
     const int nq = z1 - z0 + 4, nf = z1 - z0 + 1;
     for (int i = threadIdx.x; i < 5 * nq; i += NTHREADS) {
@@ -294,11 +301,18 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
       const int f = i / nf, j = i - f * nf;
       sBf[f][j] = p.bg_fz[f * ph.nzf + zface(ph, z0 + j)];
     }
+    if (XF && p.fcoef) {
+      for (int i = threadIdx.x; i < FZB * nq; i += NTHREADS) {
+        const int f = i / nq, j = i - f * nq;
+        int mir;
+        const int kk = zsource(ph, z0 - 2 + j, mir);
+        sZB[f][j] = p.fzb[f * ph.nz + kk];
+      }
+#pragma unroll
+      for (int d = 0; d < 3 * FZB; ++d) sFC[d][threadIdx.x] = (R)p.fcoef[d * plane + colq];
+    }
   }
   __syncthreads();
-  const size_t plane = (size_t)ph.nx * ph.ny;
-  const size_t ncell = plane * ph.nz;
-  const size_t colq = (size_t)gj * ph.nx + gi;
 
   // ring cells two columns outside the tile (x/y stencils only): the first
   // 16 lanes of each wave take one of the four sides, so that every wave
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     const bool base = ca != 0.0;
     const size_t qc = (size_t)(k > 0 ? k : 0) * plane + colq;
     const size_t qfz = (size_t)(k + 1 > 0 ? k + 1 : 0) * plane + colq;
-    double us[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0}, fo[3] = {0, 0, 0};
+    double us[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0};
     double bxs = 0.0, bys = 0.0, bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
     auto load_update = [&]() {
       if (upd) {
@@ -379,11 +393,6 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
           for (int f = 0; f < 5; ++f) u0[f] = p.U0[f * ncell + qc];
           bx0 = p.Bx0[qc];
           by0 = p.By0[qc];
-        }
-        if (XF && p.force) {
-          fo[0] = p.force[qc];
-          fo[1] = p.force[ncell + qc];
-          fo[2] = p.force[2 * ncell + qc];
         }
       }
       if (updz && base) bz0 = p.Bz0[qfz];
@@ -577,7 +586,16 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
         const int jk = k - (z0 - 2);
         double s1 = 0.0, s2 = 0.0, s3 = (us[0] - sBc[0][jk]) * ph.gz;
         double s4 = us[3] * ph.gz + sBc[4][jk];
-        if (XF && p.force) {
+        if (XF && p.fcoef) {
+          // the forcing of this cell from its column's coefficients
+          double fo[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double f = 0.0;
+#pragma unroll
+            for (int d = 0; d < FZB; ++d) f += (double)sFC[c * FZB + d][tid] * sZB[d][jk];
+            fo[c] = f;
+          }
           s1 += us[0] * fo[0];
           s2 += us[0] * fo[1];
           s3 += us[0] * fo[2];
@@ -694,7 +712,7 @@ template <typename R, bool GR>
 static void launch_stage_g(const Ctx &c, const StagePtrs &p, double a, double b, double cc,
                            double dt_host, dim3 grid) {
   dim3 block(NTHREADS);
-  if (p.force || p.flat || p.mfx || p.mfy || p.mfz)
+  if (p.fcoef || p.flat || p.mfx || p.mfy || p.mfz)
     hipLaunchKernelGGL((stage_kernel<R, GR, true>), grid, block, 0, c.stream, c.ph, p, a, b, cc,
                        dt_host, c.zseg);
   else

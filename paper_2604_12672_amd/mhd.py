@@ -268,16 +268,17 @@ class Grid:
         assert bg_cc.shape == (4, self.shape[0]) and bg_fz.shape == (4, self.nzf)
         self._check(self._L.mhd_set_background(self._h, _ptr(bg_cc, HOST), _ptr(bg_fz, HOST)))
 
-    def set_sources(self, heat=None, force=None):
+    def set_sources(self, heat=None, fmodes=None):
+        """Heating profile [nz] and forcing modes [nmodes][7] = (k_x, k_y, k_z,
+        a_x, a_y, a_z, phase) (host arrays, either may be None)."""
         if heat is not None:
             heat = np.ascontiguousarray(heat, dtype=np.float64)
             assert heat.shape == (self.shape[0],)
-        w = _where(force)
-        if force is not None and not _is_torch(force):
-            force = np.ascontiguousarray(force, dtype=np.float64)
-        if force is not None:
-            assert tuple(force.shape) == (3,) + self.shape
-        self._check(self._L.mhd_set_sources(self._h, _ptr(heat, HOST), _ptr(force, w), w))
+        n = 0
+        if fmodes is not None:
+            fmodes = np.ascontiguousarray(fmodes, dtype=np.float64).reshape(-1, 7)
+            n = len(fmodes)
+        self._check(self._L.mhd_set_sources(self._h, _ptr(heat, HOST), _ptr(fmodes, HOST), n))
 
     def set_eos_mlp(self, model):
         """Upload a paper_2604_12672_amd.eos_mlp.MLPGuess."""
@@ -322,8 +323,8 @@ class Grid:
             self.set_eos_mlp(mlp)
         if w.bg_cc is not None:
             self.set_background(w.bg_cc, w.bg_fz)
-        if w.heat is not None or w.force is not None:
-            self.set_sources(w.heat, w.force)
+        if w.heat is not None or w.fmodes is not None:
+            self.set_sources(w.heat, w.fmodes)
         ns = int(w.params.get("nspecies", 0))
         self.set_state(np.ascontiguousarray(w.U[:5]) if ns else w.U, w.Bx, w.By, w.Bz,
                        w.T if guess else None)

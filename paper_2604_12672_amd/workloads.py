@@ -45,7 +45,7 @@ class Workload:
     bg_cc: np.ndarray | None = None   # [4][nz] rho, P, gamma_e, gamma_c
     bg_fz: np.ndarray | None = None   # [4][nzf]
     heat: np.ndarray | None = None    # [nz]
-    force: np.ndarray | None = None   # [3][nz][ny][nx]
+    fmodes: np.ndarray | None = None  # [nmodes][7] forcing (k, a, phase)
     cfl: float = 0.4
     steps: int = 1
 
@@ -65,7 +65,7 @@ class Workload:
                 "T": f(self.T)}
 
     def extras(self):
-        return dict(bg_cc=self.bg_cc, bg_fz=self.bg_fz, heat=self.heat, force=self.force)
+        return dict(bg_cc=self.bg_cc, bg_fz=self.bg_fz, heat=self.heat, fmodes=self.fmodes)
 
 
 def base_params(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), **kw):
@@ -430,8 +430,10 @@ def turbulence_box(n=384, seed=3, mach=3.0, beta=1.0, rho0=1e-2, T0=1e7, cfl=0.4
     T0 and B0 z_hat with 2 P0 / B0^2 = beta; a solenoidal velocity over the
     32 integer wavevectors with 1 <= |k| <= 2 (random amplitudes projected
     perpendicular to k, seed), scaled to rms Mach `mach`; a constant forcing
-    acceleration with the same pattern and amplitude u_rms^2 / L.  The
-    background is the uniform state (rho0, P0, gamma_e0, gamma_c0)."""
+    acceleration with the same pattern and amplitude u_rms^2 / L, given as
+    the 32 Fourier modes (k, a, phase), from which the library and the
+    oracle each evaluate it.  The background is the uniform state (rho0,
+    P0, gamma_e0, gamma_c0)."""
     p = gasrad_params(n, n, n)
     xc, yc, zc, *_ = _centres(p)
     rng = np.random.default_rng(seed)
@@ -444,11 +446,13 @@ def turbulence_box(n=384, seed=3, mach=3.0, beta=1.0, rho0=1e-2, T0=1e7, cfl=0.4
     G = np.zeros((3, 5, n, n), dtype=complex)
     ex = {m: np.exp(2j * np.pi * m * xc) for m in range(-2, 3)}
     ey = {m: np.exp(2j * np.pi * m * yc) for m in range(-2, 3)}
+    modes = []
     for k in ks:
         kv = np.array(k, dtype=float)
         a = rng.normal(size=3)
         a = a - kv * (kv @ a) / (kv @ kv)
         phi = rng.uniform(0.0, 2.0 * math.pi)
+        modes.append([k[0], k[1], k[2], a[0], a[1], a[2], phi])
         plane = np.exp(1j * phi) * np.outer(ey[k[1]], ex[k[0]])
         for c in range(3):
             G[c, k[2] + 2] += a[c] * plane
@@ -469,6 +473,8 @@ def turbulence_box(n=384, seed=3, mach=3.0, beta=1.0, rho0=1e-2, T0=1e7, cfl=0.4
     cs2 = rmu * T0 + T0 * dpdT * dpdT / (rho0 * rho0 * cv)
     urms = math.sqrt(float(np.mean(np.sum(v * v, axis=0))))
     v *= mach * math.sqrt(cs2) / urms
+    # the forcing pattern is the raw velocity pattern, scaled to rms u_rms^2/L
+    fscale = (mach * math.sqrt(cs2)) ** 2 / 1.0 / urms
     b0 = math.sqrt(2.0 * P0 / beta)
     Bx = np.zeros(shp)
     By = np.zeros(shp)
@@ -479,13 +485,12 @@ def turbulence_box(n=384, seed=3, mach=3.0, beta=1.0, rho0=1e-2, T0=1e7, cfl=0.4
     gc0 = rho0 * cs2 / P0
     bg_cc = np.array([[rho0] * n, [P0] * n, [ge0] * n, [gc0] * n])
     bg_fz = bg_cc.copy()
-    force = None
+    fmodes = None
     if forcing:
-        u_rms = mach * math.sqrt(cs2)
-        force = v / np.sqrt(np.mean(np.sum(v * v, axis=0))) * (u_rms ** 2 / 1.0)
-        force = np.ascontiguousarray(force)
+        fmodes = np.array(modes, dtype=np.float64)
+        fmodes[:, 3:6] *= fscale
     return Workload("turbulence_box", p, U, Bx, By, Bz, T=T, bg_cc=bg_cc, bg_fz=bg_fz,
-                    force=force, cfl=cfl, steps=steps)
+                    fmodes=fmodes, cfl=cfl, steps=steps)
 
 
 # --------------------------------------------------------------------------
@@ -531,7 +536,7 @@ def add_species(w, ns, seed=9, kmax=2, contrast=0.9):
     Xl = f / f.sum(axis=0)
     U = np.ascontiguousarray(np.concatenate([w.U[:5], w.U[0][None] * Xl], axis=0))
     return Workload(w.name + f"+{ns}sp", p, U, w.Bx, w.By, w.Bz, T=w.T, bg_cc=w.bg_cc,
-                    bg_fz=w.bg_fz, heat=w.heat, force=w.force, cfl=w.cfl, steps=w.steps)
+                    bg_fz=w.bg_fz, heat=w.heat, fmodes=w.fmodes, cfl=w.cfl, steps=w.steps)
 
 
 def smooth_box(nx, ny, nz, seed=7, bcz=BC_PERIODIC, amp_v=0.3, amp_b=0.4, kmax=2, eos=EOS_IDEAL,

@@ -64,7 +64,7 @@ def rel_errors(out, ref):
 
 def _with(w, **kw):
     return wl.Workload(w.name, dict(w.params, **kw), w.U, w.Bx, w.By, w.Bz, T=w.T,
-                       bg_cc=w.bg_cc, bg_fz=w.bg_fz, heat=w.heat, force=w.force, cfl=w.cfl)
+                       bg_cc=w.bg_cc, bg_fz=w.bg_fz, heat=w.heat, fmodes=w.fmodes, cfl=w.cfl)
 
 
 def run_pair(mhd, w, nsteps, precision=0, cfl=None):

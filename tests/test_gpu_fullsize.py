@@ -241,7 +241,7 @@ def test_turbulence_384_invariants(mhd):
     assert abs(d1["total"][0] - d0["total"][0]) <= 1e-12 * abs(d0["total"][0])
     assert abs(d1["bflux_x0"] - d0["bflux_x0"]) <= 1e-14 * d0["bface_max"] * 384 * 384
     assert d1["divb_max"] < 1e-12
-    w.force = None
+    w.fmodes = None
     g = mhd.Grid(w.params, precision=1, eos_guess=mhd.GUESS_MLP)
     g.load(w, mlp=mlp)
     d0 = g.diagnostics()

@@ -1,8 +1,8 @@
 """The stage kernel is compiled twice: without and with the code of the
-optional features (forcing field, shock-flattening flags, species mass
+optional features (forcing modes, shock-flattening flags, species mass
 fluxes).  Where a feature is present but changes nothing, the two variants
 must give the same fluid state bit for bit:
-- a forcing field of zeros (the sources add exact zeros),
+- forcing modes of zero amplitude (the sources add exact zeros),
 - flattening with a detector threshold no cell reaches (no flags: every
   face takes LHLLD, every cell its own reconstruction),
 - passive species (the fluid does not see them).
@@ -58,8 +58,11 @@ def test_zero_forcing_matches_no_forcing(mhd, precision):
     w = wl.smooth_box(20, 17, 13, bcz=1)
     dts = [cfl_dt(w)] * 3
     a = run(mhd, w, dts, precision)
+    # forcing modes of zero amplitude (every wavenumber kind of the basis)
+    zero = [[kx, ky, kz, 0.0, 0.0, 0.0, 0.3] for kx, ky, kz in
+            ((1, 0, 0), (0, 1, 1), (1, -1, -2), (2, 1, 2), (0, 0, -1))]
     wf = wl.Workload(w.name, w.params, w.U, w.Bx, w.By, w.Bz, bg_cc=w.bg_cc, bg_fz=w.bg_fz,
-                     force=np.zeros((3,) + w.shape), cfl=w.cfl)
+                     fmodes=np.array(zero), cfl=w.cfl)
     b = run(mhd, wf, dts, precision)
     assert same(a, b)
 

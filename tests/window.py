@@ -68,8 +68,12 @@ def extract(w, i0, j0, k0, nw, nzw, state=None):
             w.bg_fz[:, np.arange(k0, k0 + nzw + 1)] if reflect else w.bg_fz[:, kk])
     if w.heat is not None:
         ext["heat"] = np.ascontiguousarray(w.heat[kk])
-    if w.force is not None:
-        ext["force"] = np.ascontiguousarray(w.force[(slice(None),) + sel])
+    if w.fmodes is not None:
+        # the forcing of the full box, evaluated at the window's cells: the
+        # window's first corner sits at (i0, j0, k0) cells from the box's
+        ext["fmodes"] = w.fmodes
+        ext["forcing_origin"] = (i0 * dx[0], j0 * dx[1], k0 * dx[2])
+        ext["forcing_period"] = tuple(p["hi"][a] - p["lo"][a] for a in range(3))
     return q, {"U": U, "Bx": Bx, "By": By, "Bz": Bz, "T": T}, ext, (kk, jj, ii)
 
 
