@@ -118,7 +118,8 @@ typedef struct {
   double total[5];        /* sums over cells of rho, m_x, m_y, m_z, E          */
   double bflux_x0;        /* sum of Bx over the plane x_{-1/2}                 */
   int64_t newton_iters;   /* Newton steps of the owned cells, summed over the
-                             stages of the last step                          */
+                             stages of the last step (with the learned guess
+                             including the polish in the guess kernel)        */
   int64_t newton_max;     /* largest Newton count of one cell-stage, last step */
   int64_t fallbacks;      /* cell-stages that needed the bracketed solve,
                              last step                                        */

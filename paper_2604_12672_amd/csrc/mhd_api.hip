@@ -588,12 +588,13 @@ static int run_step(mhd_ctx *h, double dt_host, const double *dt_dev) {
     const bool learned = c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP;
     const bool reuse = s == 0 && (!learned || c.t0_current) && (!c.d.flatten || c.p_current);
     if (learned && !(reuse && c.t0_current)) {
-      // learned guesses of the stage input, polished by Newton in the stage
-      // (with flattening already here, where the pressure is taken too);
-      // the first stage skips this when the CFL kernel left the converged
-      // temperatures of its input
+      // learned guesses of the stage input, polished by FP64 Newton in the
+      // guess kernel (with flattening the pressure is taken there too), so
+      // the stage starts from converged temperatures; the first stage skips
+      // this when the CFL kernel left the converged temperatures of its
+      // input
       HIPCHK(h, mhd::launch_mlp_guess(c, p.Us, p.Bxs, p.Bys, p.Bzs, c.T[0],
-                                      c.d.flatten ? c.shock_p : nullptr));
+                                      c.d.flatten ? c.shock_p : nullptr, true, c.nstats));
     }
     p.Tin = prev_t ? c.T[c.tcur] : (learned ? c.T[0] : nullptr);
     p.Tout = prev_t ? c.T[1 - c.tcur] : nullptr;
@@ -712,7 +713,8 @@ int mhd_shock_flags(mhd_ctx *h, uint8_t *flags, int32_t where) {
     return fail(h, MHD_ERR_STATE, "learned guess selected but mhd_set_eos_mlp not called");
   const int s = c.cur;
   if (c.ph.gasrad && c.d.eos_guess == MHD_GUESS_MLP)
-    HIPCHK(h, mhd::launch_mlp_guess(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[0], c.shock_p));
+    HIPCHK(h, mhd::launch_mlp_guess(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s], c.T[0], c.shock_p,
+                                    true, nullptr));
   else
     HIPCHK(h, mhd::launch_shock_pressure(c, c.U[s], c.Bx[s], c.By[s], c.Bz[s],
                                          c.ph.gasrad ? c.T[c.tcur] : nullptr, c.ph.newton_maxit));

@@ -172,7 +172,8 @@ int stage_blocks_per_cu(const Ctx &c);
 // learned guesses into Tg; with P (nullable) also Newton-polished there and
 // the thermal pressure into P
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, double *Tg, double *P = nullptr);
+                            const double *Bz, double *Tg, double *P, bool polish,
+                            unsigned long long *stats);
 hipError_t launch_diff_init(const Ctx &c, const double *U, const double *Bx, const double *By,
                             const double *Bz, const double *Tg);
 hipError_t launch_diff_stage(const Ctx &c, const double *U, const double *Ta, const double *chia,

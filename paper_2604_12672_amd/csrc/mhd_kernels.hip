@@ -948,17 +948,22 @@ hipError_t launch_init_temperature(const Ctx &c, const double *U,
 // learned mode): the stage kernel reads it as its temperature guess
 // ---------------------------------------------------------------------------
 
-// With P != nullptr (shock flattening) the guess is polished by Newton
-// right here and the converged temperature is stored in its place, together
-// with the thermal pressure the flattening detector needs: the stage input
-// is then read once for both, and the stage's own Newton starts converged.
+// With polish the guess is polished by FP64 Newton right here (at most
+// newton_maxit_mlp steps, then the bracketed solve) and the converged
+// temperature is stored in its place, so the stage's own Newton starts
+// converged: the iterations run in this small kernel at full occupancy
+// instead of in the register-bound stage.  Their statistics go to stats
+// (nullable).  With P != nullptr (shock flattening) the thermal pressure
+// the detector needs is stored as well.
 __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *__restrict__ U,
                                                         const double *__restrict__ Bx,
                                                         const double *__restrict__ By,
                                                         const double *__restrict__ Bz,
                                                         const void *mlp,
                                                         double *__restrict__ Tg,
-                                                        double *__restrict__ P, int *flags) {
+                                                        double *__restrict__ P, int *flags,
+                                                        int polish,
+                                                        unsigned long long *stats) {
   __shared__ __attribute__((aligned(16))) char sMlpRaw[sizeof(MlpLds)];
   const MlpLds &sMlp = *reinterpret_cast<const MlpLds *>(sMlpRaw);
   stage_mlp(mlp, sMlpRaw, threadIdx.x, 256);
@@ -988,6 +993,7 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
   const size_t stride = (size_t)gridDim.x * 256;
   size_t base = (size_t)blockIdx.x * 256;
   double un[5] = {1, 0, 0, 0, 1}, fn[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long nit = 0, nmax = 0, nfb = 0;
   if (base < n) fetch(base + threadIdx.x < n ? base + threadIdx.x : n - 1, un, fn);
   for (; base < n; base += stride) {
     const bool valid = base + threadIdx.x < n;
@@ -1005,7 +1011,7 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
     mlp_inputs(ph, u[0], e, x0, x1);
     const double t = mlp_guess_wave(ph, sMlp, x0, x1, lane);
     if (!valid) continue;
-    if (!P) {
+    if (!polish) {
       Tg[q] = t;
       continue;
     }
@@ -1013,17 +1019,48 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
     PrimOut o;
     cons2prim<true>(ph, u, b, t, zero_bg, o, ph.newton_maxit_mlp);
     if (o.bad) atomicOr(flags, o.bad);
+    nit += o.iters;
+    nmax = o.iters > nmax ? o.iters : nmax;
+    nfb += o.fallback;
     Tg[q] = o.T;
-    P[q] = o.w[Q_P];  // full pressure: the background passed is zero
+    if (P) P[q] = o.w[Q_P];  // full pressure: the background passed is zero
+  }
+  if (stats) {
+    // block totals of the Newton statistics
+    __shared__ unsigned long long s_it[4], s_fb[4], s_mx[4];
+    for (int o = 32; o > 0; o >>= 1) {
+      nit += __shfl_xor(nit, o);
+      nfb += __shfl_xor(nfb, o);
+      const unsigned long long m = __shfl_xor(nmax, o);
+      nmax = m > nmax ? m : nmax;
+    }
+    if (lane == 0) {
+      s_it[threadIdx.x >> 6] = nit;
+      s_fb[threadIdx.x >> 6] = nfb;
+      s_mx[threadIdx.x >> 6] = nmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long a = 0, f = 0, m = 0;
+      for (int w = 0; w < 4; ++w) {
+        a += s_it[w];
+        f += s_fb[w];
+        m = s_mx[w] > m ? s_mx[w] : m;
+      }
+      atomicAdd(&stats[0], a);
+      atomicMax(&stats[1], m);
+      atomicAdd(&stats[2], f);
+    }
   }
 }
 
 hipError_t launch_mlp_guess(const Ctx &c, const double *U, const double *Bx, const double *By,
-                            const double *Bz, double *Tg, double *P) {
+                            const double *Bz, double *Tg, double *P, bool polish,
+                            unsigned long long *stats) {
   long long nb = (long long)((c.ncell + 255) / 256);
   nb = nb < 8192 ? nb : 8192;
   hipLaunchKernelGGL(mlp_guess_kernel, dim3((unsigned)nb), dim3(256), 0, c.stream, c.ph, U, Bx,
-                     By, Bz, c.mlp, Tg, P, c.flags);
+                     By, Bz, c.mlp, Tg, P, c.flags, polish ? 1 : 0, stats);
   return hipGetLastError();
 }
 

