@@ -55,7 +55,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "aba9d0b134a09e97": {"fp64": (1484746.6, 1107937.6), "split": (1836621.0, 1223248.9)},
+    "9b47a6759f433b3d": {"fp64": (1483967.0, 1107301.4), "split": (1820975.2, 1222552.2)},
 }
 
 
@@ -65,7 +65,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "aba9d0b134a09e97": {"fp64": 911465283, "split": 624704211},
+    "9b47a6759f433b3d": {"fp64": 911465283, "split": 624704211},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
