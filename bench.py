@@ -73,7 +73,7 @@ VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 # HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch, averaged over a super step) for the digest of its sources
 RKL2_TRAFFIC_KIB = {
-    "c14bb0c72755b560": {"eint": (501483.1, 397803.5), "temp": (517077.8, 266731.5)},
+    "7b3e56e4f5753893": {"eint": (504232.8, 397803.5), "temp": (511745.5, 266731.5)},
 }
 
 
