@@ -105,9 +105,10 @@ def traffic_bytes(path):
 
 def gpu_run(mhd, w, precision, steps, warmup, mlp=None):
     """Whole-step throughput with mhd_advance (device dt, no host round
-    trip), then the stage kernel's duration from HIP events on the library's
-    stream around fixed-dt steps (only the stage launches run between the
-    events)."""
+    trip), then the stage's duration from HIP events on the library's stream
+    around fixed-dt steps: only the launches of the stages run between the
+    events (the stage kernel, and the per-stage guess or flag kernels where
+    the workload has them; timed_kernels names them)."""
     import torch
     guess = mhd.GUESS_MLP if mlp is not None else mhd.GUESS_PREV_T
     g = mhd.Grid(w.params, precision=precision, eos_guess=guess)
@@ -159,6 +160,19 @@ def extra_bytes(w, learned):
     return BYTES_GUESS_ARRAY if (learned and w.T is not None) else 0.0
 
 
+def timed_kernels(w, learned):
+    """The launches between the HIP events of gpu_run's stage timing: the
+    stage kernel, and per stage the learned-guess kernel (learned guess)
+    and the pressure and flag passes (shock flattening)."""
+    k = ["stage_kernel"]
+    if learned and w.T is not None:
+        k.append("mlp_guess_kernel")
+    if w.params.get("flatten"):
+        k += ["shock_pressure_kernel" if not learned else "mlp_guess_kernel (pressure)",
+              "shock_flag_kernel"]
+    return k
+
+
 def roofline(w, stage_ms, path, learned=False):
     per_zone = stage_bytes(w, learned)
     per_launch = per_zone * w.ncells
@@ -168,6 +182,7 @@ def roofline(w, stage_ms, path, learned=False):
            "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": None if tr is None else round(tr),
            "kernel": "stage_kernel", "stage_ms": round(stage_ms, 4),
+           "timed": timed_kernels(w, learned),
            "bytes_per_zone_stage": per_zone, "algorithmic_bytes_per_launch": round(per_launch)}
     xb = extra_bytes(w, learned)
     if xb:
