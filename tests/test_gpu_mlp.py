@@ -45,8 +45,16 @@ def test_device_guess_matches_emulation(mhd, model):
     T0 = T0d.cpu().numpy()
     em = model.predict_log10T(rho, e)
     d = np.abs(np.log10(T0) - em)
-    print(f"guess vs emulation: median {np.median(d):.2e} max {d.max():.2e} dex", flush=True)
-    assert np.median(d) < 1e-4 and d.max() < 1e-2
+    p99, p999 = np.percentile(d, 99), np.percentile(d, 99.9)
+    print(f"guess vs emulation: median {np.median(d):.2e} p99 {p99:.2e} p99.9 {p999:.2e} "
+          f"max {d.max():.2e} dex", flush=True)
+    # the same BF16 arithmetic on both sides: FP32 accumulation order differs,
+    # which now and then flips the BF16 rounding of one hidden activation (the
+    # rare cells in the tail); any slip in the layer wiring moves the median
+    # by orders of magnitude (measured: median 1.8e-7, p99 5.9e-7, p99.9
+    # 1.4e-6, max 3.1e-3 dex)
+    assert np.median(d) < 2e-6, np.median(d)
+    assert p99 < 5e-6 and p999 < 3e-5 and d.max() < 1e-2, (p99, p999, d.max())
     ge = np.abs(np.log10(T0) - np.log10(T))
     print(f"guess error: mean {ge.mean():.2e} max {ge.max():.2e} dex; newton steps "
           f"{stats[0] / n:.2f}/sample, max {stats[1]}, fallbacks {stats[2]}", flush=True)
