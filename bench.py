@@ -252,9 +252,11 @@ def eos_bench(mhd, model, n):
 
 
 def _rel_l2(a, b):
+    """||a - b|| / ||b||, or ||a|| where the reference field is zero."""
     import numpy as np
     den = float(np.sqrt(np.sum(b * b)))
-    return float(np.sqrt(np.sum((a - b) ** 2))) / den if den > 0 else None
+    num = float(np.sqrt(np.sum((a - b) ** 2)))
+    return num / den if den > 0 else num
 
 
 FIELD_NAMES = [("U", 0, "rho"), ("U", 1, "m_x"), ("U", 2, "m_y"), ("U", 3, "m_z"), ("U", 4, "E"),
@@ -300,6 +302,45 @@ def split_error(mhd, n, steps):
                 "workload": f"stratified box {n}^3 with heating and cooling (q = 1e-6 of the "
                             f"energy flux in the bottom and top 10 %)"})
     return res
+
+
+def learned_error(mhd, model, steps):
+    """The FP32+learned-EOS step against the FP64 oracle after `steps`
+    steps on the workloads with the learned guess: the gas + radiation box
+    (config 3's recipe) at 64^3 and the forced Mach-3 turbulence box
+    (config 4's recipe) at 48^3, sizes at which the host oracle takes
+    seconds; the GPU on the oracle's dt sequence."""
+    from oracle import orc
+    from paper_2604_12672_amd import workloads as wl
+    out = {}
+    for name, w in (("gasrad_64", wl.gasrad_box(64)), ("turbulence_48", wl.turbulence_box(48))):
+        o = orc.Oracle(w.params, **w.extras())
+        ref = w.state()
+        dts = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dt = o.compute_dt(ref, w.cfl)
+            o.step(ref, dt)
+            dts.append(dt)
+        oracle_s = time.perf_counter() - t0
+        g = mhd.Grid(w.params, precision=mhd.PREC_SPLIT, eos_guess=mhd.GUESS_MLP)
+        g.load(w, mlp=model)
+        for dt in dts:
+            g.step(dt)
+        st = g.get_state()
+        d = g.diagnostics()
+        g.close()
+        errs = {}
+        for key, c, fname in FIELD_NAMES:
+            a = st[key] if c is None else st[key][c]
+            b = ref[key] if c is None else ref[key][c]
+            errs[fname] = _rel_l2(a, b)
+        out[name] = {"steps": steps, "rel_l2_vs_oracle": errs,
+                     "max_rel_l2": max(v for v in errs.values() if v is not None),
+                     "divb_max": d["divb_max"], "fallback_cell_stages_last_step": d["fallbacks"],
+                     "oracle_s": round(oracle_s, 1)}
+    out["path"] = "split precision with the learned EOS guess, FP64 oracle on the host as reference"
+    return out
 
 
 # algorithmic bytes per cell of one RKL2 stage j >= 2.  Internal-energy form:
@@ -741,6 +782,8 @@ def main():
             f"{args.split_steps} steps")
         out["split_error"] = split_error(mhd, args.split_n, args.split_steps)
         log(f"bench: split error vs oracle {out['split_error']['split']['rel_l2_vs_oracle']}")
+        log("bench: split + learned against the oracle, gas+radiation 64^3 and turbulence 48^3")
+        out["learned_split_error"] = learned_error(mhd, model, args.split_steps)
         out["turbulence"], out["turbulence_flattened"] = turbulence_bench(mhd, model, args)
     if not args.no_extras and not args.only:
         out["blast_flattened"] = blast_bench(mhd, args.n, args.steps, args.warmup)
