@@ -45,6 +45,10 @@ BYTES_T_STAGE = 16.0
 # learned guess it reads from the guess kernel's array
 BYTES_GUESS_ARRAY = 8.0
 METRIC = "zone-updates/s (3D MHD 256^3) FP64 vs FP32+learned-EOS; % HBM roofline"
+# the learned guess network 2 -> 64 -> 64 -> 1: multiply-adds per sample, and
+# the dense BF16 matrix peak of the chip (TFLOP/s)
+MLP_MACS = 2 * 64 + 64 * 64 + 64
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 # HBM traffic of the stage kernel from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs (average KiB per dispatch over the timed launches), keyed
@@ -244,6 +248,16 @@ def eos_bench(mhd, model, n):
             d = np.abs(np.log10(T0.cpu().numpy()) - np.log10(T))
             res["guess_mean_abs_dlog10T"] = float(d.mean())
             res["guess_max_abs_dlog10T"] = float(d.max())
+            # the network's matrix work: 4 288 multiply-adds per sample
+            # (64 x 64 + 64 x 2 + 64), priced against the BF16 MFMA peak; the
+            # timed call also runs the FP64 Newton polish, so this is a lower
+            # bound on the rate of the matrix passes themselves
+            tf = 2.0 * MLP_MACS * n / (ms * 1e-3) / 1e12
+            res["mfma_roofline"] = {"bound": "mfma", "achieved": round(tf, 2),
+                                    "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": round(tf / BF16_MFMA_PEAK_TFLOPS, 4),
+                                    "flop_per_sample": 2 * MLP_MACS,
+                                    "note": "network + Newton polish in the timed call"}
         out[name] = res
         log(f"bench: eos {name}: {res}")
     out["speedup_learned_vs_bracketed"] = round(out["bracketed"]["ms"] / out["learned"]["ms"], 3)
