@@ -440,17 +440,29 @@ int mhd_set_sources(mhd_ctx *h, const double *heat, const double *fmodes, int32_
     const double pi2 = 6.283185307179586476925286766559;
     const size_t nxy = (size_t)nx * ny;
     std::vector<double> coef((size_t)3 * mhd::FZB * nxy, 0.0), zb((size_t)mhd::FZB * nz);
+    // cos and sin of alpha = a_x + a_y with a_x = 2 pi k_x X + phi and
+    // a_y = 2 pi k_y Y from per-axis tables (angle addition), so a mode
+    // costs nx + ny sine/cosine pairs instead of nx ny
+    std::vector<double> cx(nx), sx(nx), cy(ny), sy(ny);
     for (int m = 0; m < nmodes; ++m) {
       const double *md = fmodes + 7 * m;
       const int kz = (int)md[2];
       const int d = kz == 0 ? 0 : (kz == 1 || kz == -1 ? 1 : 3);
       const double sg = kz < 0 ? -1.0 : 1.0;
+      for (int i = 0; i < nx; ++i) {
+        const double ax = pi2 * md[0] * ((i + 0.5) / nx) + md[6];
+        cx[i] = std::cos(ax);
+        sx[i] = std::sin(ax);
+      }
       for (int j = 0; j < ny; ++j) {
-        const double Y = (j + 0.5) / ny;
+        const double ay = pi2 * md[1] * ((j + 0.5) / ny);
+        cy[j] = std::cos(ay);
+        sy[j] = std::sin(ay);
+      }
+      for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
-          const double X = (i + 0.5) / nx;
-          const double al = pi2 * (md[0] * X + md[1] * Y) + md[6];
-          const double ca = std::cos(al), sa = std::sin(al);
+          const double ca = cx[i] * cy[j] - sx[i] * sy[j];
+          const double sa = sx[i] * cy[j] + cx[i] * sy[j];
           const size_t q = (size_t)j * nx + i;
           for (int cc = 0; cc < 3; ++cc) {
             double *cf = coef.data() + (size_t)(cc * mhd::FZB) * nxy + q;
