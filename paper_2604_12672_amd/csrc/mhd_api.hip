@@ -795,8 +795,8 @@ int mhd_set_eos_mlp(mhd_ctx *h, const float *w1, const float *b1, const uint16_t
     return x;
   };
   uint16_t *a1 = (uint16_t *)buf.data();  // [2][64][4]
-  uint16_t *a2 = a1 + 2 * 64 * 4;          // [2][8][64][4]
-  float *c2 = (float *)(a2 + 2 * 8 * 64 * 4);  // [2][16][64]
+  uint16_t *a2 = a1 + 2 * 64 * 4;          // [2][4][64][8]
+  float *c2 = (float *)(a2 + 2 * 4 * 64 * 8);  // [2][16][64]
   uint16_t *w3b = (uint16_t *)(c2 + 2 * 16 * 64);  // [64]
   for (int mb = 0; mb < 2; ++mb)
     for (int l = 0; l < 64; ++l) {
@@ -810,9 +810,12 @@ int mhd_set_eos_mlp(mhd_ctx *h, const float *w1, const float *b1, const uint16_t
       } else {
         d[0] = w1l; d[1] = w1h; d[2] = bh; d[3] = bl;
       }
-      for (int kb = 0; kb < 8; ++kb)
-        for (int t = 0; t < 4; ++t)
-          a2[((mb * 8 + kb) * 64 + l) * 4 + t] = w2[m * 64 + 8 * kb + 4 * (l / 32) + t];
+      // K block q of the K = 16 layer-2 product: value t of lane l is the
+      // hidden unit layer 1 leaves in that lane's register 4(2q + t/4) + t%4
+      for (int q = 0; q < 4; ++q)
+        for (int t = 0; t < 8; ++t)
+          a2[((mb * 4 + q) * 64 + l) * 8 + t] =
+              w2[m * 64 + 8 * (2 * q + t / 4) + 4 * (l / 32) + t % 4];
       for (int r = 0; r < 16; ++r)
         c2[(mb * 16 + r) * 64 + l] = b2[32 * mb + 8 * (r / 4) + 4 * (l / 32) + r % 4];
     }

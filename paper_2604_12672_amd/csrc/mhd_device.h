@@ -259,25 +259,35 @@ __device__ __forceinline__ void cons2prim(const Phys &ph, const double u[5],
 // ---------------------------------------------------------------------------
 // learned initial guess of T(rho, e_int) on the matrix cores
 //
-// A 2 -> 64 -> 64 -> 1 ReLU network evaluated for 32 cells per pass with
-// v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32, FP32 accumulation).
-// Operand layout (lane l, t = 0..3, r = 0..15):
+// A 2 -> 64 -> 64 -> 1 ReLU network evaluated for 32 cells per pass.
+// Layer 1 runs on v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32, FP32
+// accumulation), layer 2 on gfx950's v_mfma_f32_32x32x16_bf16 (K = 16 per
+// instruction at the same instruction time: half the passes).  Operand
+// layout of the K = 8 form (lane l, t = 0..3, r = 0..15):
 //   A: A[l%32][4(l/32) + t]     B: B[4(l/32) + t][l%32]
 //   D: row 8(r/4) + 4(l/32) + r%4, column l%32
-// so the accumulator of one layer, taken four registers at a time, is the B
-// operand of the next (rows = hidden units, columns = cells).  Layer 1 folds
-// its bias into K = 8 rows (x0h, x0h, x0l, x1h | x1h, x1l, 1, 1) against
-// (w0h, w0l, w0h, w1h | w1l, w1h, b1h, b1l): hi/lo BF16 pairs keep about 16
-// bits of the inputs and of W1, b1.  Layer 3 (64 -> 1) takes BF16 dot
-// products of the layer-2 registers with W3 pairs on the vector unit.
+// so the accumulator of one layer, taken four registers at a time, holds
+// the hidden units 8j + 4(l/32) + 0..3 of its column (rows = hidden units,
+// columns = cells).  The K = 16 form takes eight values per lane and each
+// lane half supplies its own eight K rows, the same way in A and in B; so
+// the B operand of K block q is the two four-register groups 2q and 2q+1 of
+// the layer-1 accumulator as they are, and the A operand (W2) is packed with
+// the matching hidden units: value t of lane l is unit
+// 8(2q + t/4) + 4(l/32) + t%4.  Layer 1 folds its bias into K = 8 rows
+// (x0h, x0h, x0l, x1h | x1h, x1l, 1, 1) against (w0h, w0l, w0h, w1h | w1l,
+// w1h, b1h, b1l): hi/lo BF16 pairs keep about 16 bits of the inputs and of
+// W1, b1.  Layer 3 (64 -> 1) takes BF16 dot products of the layer-2
+// registers with W3 pairs on the vector unit.
 // ---------------------------------------------------------------------------
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 struct MlpLds {        // host-packed fragments, staged in LDS per block
   v4s a1[2][64];       // layer 1, per output block mb and lane
-  v4s a2[2][8][64];    // layer 2: W2[32mb + l%32][8kb + 4(l/32) + t]
+  v8s a2[2][4][64];    // layer 2: W2[32mb + l%32][8(2q + t/4) + 4(l/32) + t%4]
   float c2[2][16][64]; // layer-2 accumulator start: b2 in the D layout
   short w3[64];        // layer 3 weights (BF16 bits)
 };
@@ -327,9 +337,13 @@ __device__ __forceinline__ float mlp_pass(const MlpLds &S, float x0, float x1, i
     d1[r] = S.c2[1][r][lane];
   }
 #pragma unroll
-  for (int kb = 0; kb < 8; ++kb) {
-    d0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[0][kb][lane], h[kb], d0, 0, 0, 0);
-    d1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(S.a2[1][kb][lane], h[kb], d1, 0, 0, 0);
+  for (int q = 0; q < 4; ++q) {
+    const v8s hq = __builtin_shufflevector(h[2 * q], h[2 * q + 1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const v8bf b = __builtin_bit_cast(v8bf, hq);
+    d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, S.a2[0][q][lane]), b,
+                                                 d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, S.a2[1][q][lane]), b,
+                                                 d1, 0, 0, 0);
   }
   // layer 3, 64 -> 1: this lane holds hidden units 8j + 4(l/32) + t (d0)
   // and 32 + the same (d1) of its cell; BF16 dot products of register pairs
