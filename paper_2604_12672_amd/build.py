@@ -16,9 +16,15 @@ SOURCES = ["mhd_api.hip", "mhd_kernels.hip", "mhd_diffusion.hip", "mhd_flatten.h
            "mhd_species.hip", "mhd_mathcheck.hip", "mhd_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -amdgpu-mfma-vgpr-form: the matrix instructions of the guess network
+# write their results to ordinary VGPRs, so the vector work that packs them
+# for the next layer reads them directly instead of copying each value out
+# of the accumulation registers first (the kernels without matrix
+# instructions are unaffected).
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-result",
 ]
 

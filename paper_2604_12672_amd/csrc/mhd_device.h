@@ -292,26 +292,38 @@ struct MlpLds {        // host-packed fragments, staged in LDS per block
   short w3[64];        // layer 3 weights (BF16 bits)
 };
 
-__device__ __forceinline__ short bf16_bits(float x) {
-  return __builtin_bit_cast(short, (__bf16)x);
-}
-__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
-__device__ __forceinline__ v4s pack_bf16(float a, float b, float c, float d) {
-  v4s r;
-  r[0] = bf16_bits(a);
-  r[1] = bf16_bits(b);
-  r[2] = bf16_bits(c);
-  r[3] = bf16_bits(d);
-  return r;
-}
-
-// ReLU on packed BF16: a negative BF16 is a negative 16-bit integer, so an
-// integer max with 0 clears it (v_pk_max_i16, two values per instruction).
 typedef short v2s __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ v4s relu_bf16(v4s x) { return __builtin_elementwise_max(x, (v4s)0); }
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
+// two FP32 values to one register of packed BF16 (round to nearest even),
+// a in the low half: one v_cvt_pk_bf16_f32
+__device__ __forceinline__ unsigned pack2_bf16(float a, float b) {
+  v2bf r;
+  r[0] = (__bf16)a;
+  r[1] = (__bf16)b;
+  return __builtin_bit_cast(unsigned, r);
+}
+__device__ __forceinline__ v4s pack_bf16(float a, float b, float c, float d) {
+  const v2u w = {pack2_bf16(a, b), pack2_bf16(c, d)};
+  return __builtin_bit_cast(v4s, w);
+}
+
+// ReLU of two FP32 values into one register of packed BF16: the pair is
+// converted in one instruction, then a negative BF16 (a negative 16-bit
+// integer, -0 included) is cleared by an integer max with 0 on both halves
+// (v_pk_max_i16).  The empty asm statement (no instruction) hides the
+// packed register from the instruction combiner, which would otherwise
+// split the pair into two single conversions and a permute.
+__device__ __forceinline__ unsigned pack2_relu(float a, float b) {
+  unsigned u = pack2_bf16(a, b);
+  asm("" : "+v"(u));
+  return __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(v2s, u), (v2s)0));
+}
 __device__ __forceinline__ v4s pack_relu(const v16f &d, int j) {
-  return relu_bf16(pack_bf16(d[4 * j], d[4 * j + 1], d[4 * j + 2], d[4 * j + 3]));
+  const v2u w = {pack2_relu(d[4 * j], d[4 * j + 1]), pack2_relu(d[4 * j + 2], d[4 * j + 3])};
+  return __builtin_bit_cast(v4s, w);
 }
 
 // One pass over the 32 cells held by lanes 0..31 (lanes l and l+32 carry
