@@ -59,7 +59,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "ce4b9ac9d8414a39": {"fp64": (1484686.2, 1107725.4), "split": (1814498.7, 1221938.0)},
+    "be01a2059f9c1901": {"fp64": (1485790.0, 1108687.9), "split": (1818705.7, 1223683.1)},
 }
 
 
@@ -69,7 +69,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "ce4b9ac9d8414a39": {"fp64": 911465283, "split": 624704211},
+    "be01a2059f9c1901": {"fp64": 911465283, "split": 624704211},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
@@ -77,7 +77,7 @@ VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 # HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch, averaged over a super step) for the digest of its sources
 RKL2_TRAFFIC_KIB = {
-    "6a806e7f95855819": {"eint": (501559.6, 397803.5), "temp": (502761.3, 266731.5)},
+    "87fe602be53c3be4": {"eint": (501491.7, 397803.5), "temp": (502751.0, 266731.5)},
 }
 
 
