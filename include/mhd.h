@@ -170,9 +170,10 @@ int mhd_set_sources(mhd_ctx *ctx, const double *heat, const double *fmodes,
    norm [6].  Layers 1 and 2 run on the matrix cores (BF16 operands, FP32
    accumulation), layer 3 as BF16 dot products on the vector unit, in a
    guess kernel that fills the context's guess array from the stage input
-   before each stage; the stage then polishes in FP64 Newton (at most 8
-   steps, then the bracketed solve).  Must precede the
-   first step.  Copies the weights. */
+   before each stage; the same kernel polishes each guess by FP64 Newton
+   (at most 8 steps, then the bracketed solve) and stores the converged
+   temperature, which the stage's own Newton iteration starts from.  Must
+   precede the first step.  Copies the weights. */
 int mhd_set_eos_mlp(mhd_ctx *ctx, const float *w1, const float *b1,
                     const uint16_t *w2, const float *b2, const uint16_t *w3,
                     float b3, const double *norm);

@@ -3,11 +3,12 @@ EOS (offline training; not part of the timed step).
 
 The guess T0 = 10^MLP(log10 rho, log10 e_int) comes from a 2 -> 64 -> 64 -> 1
 ReLU network.  On the GPU a separate guess kernel evaluates it before each
-stage: layers 1 and 2 on the matrix cores (v_mfma_f32_32x32x8_bf16, FP32
-accumulation), layer 3 as BF16 dot products on the vector unit
-(v_dot2c_f32_bf16); the stage then polishes the guess by the FP64 Newton
-iteration (which fixes T to the 1e-11 tolerance whatever the guess), with
-the bracketed solve as fallback.
+stage: layer 1 on v_mfma_f32_32x32x8_bf16, layer 2 on
+v_mfma_f32_32x32x16_bf16 (FP32 accumulation), layer 3 as BF16 dot products
+on the vector unit (v_dot2c_f32_bf16); the same kernel then polishes the
+guess by the FP64 Newton iteration (which fixes T to the 1e-11 tolerance
+whatever the guess), with the bracketed solve as fallback, and the stage
+starts from the polished temperature.
 
 Training data: log-uniform rho in [1e-2, 1e2] and T in [1e5, 1e8] (seeded),
 e_int from the forward EOS e = R T/((gamma-1) mu) + a T^4/rho; inputs and
