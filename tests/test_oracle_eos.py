@@ -126,3 +126,31 @@ def test_gamma_limits():
     P, e, cv, cs2 = o.eos_thermo(1.0, 1e7)
     assert cs2 / P == pytest.approx(4.0 / 3.0, rel=1e-12)
     assert P / e + 1 == pytest.approx(4.0 / 3.0, rel=1e-12)
+
+
+def test_newton_steps_against_guess_error():
+    """Newton's quadratic convergence in the inversion (Sect. 2.2): the steps
+    it takes fall as the guess improves, and a guess within 1e-8 dex
+    converges in one step.  The table is what a learned guess would have
+    to reach to save steps (the polish of a BF16 network, about 3e-3 dex,
+    takes about 2.2 steps on average)."""
+    p = _params()
+    o = orc.Oracle(p)
+    rho_s, T_s = wl.eos_samples(300, seed=7)
+    rng = np.random.default_rng(7)
+    sign = rng.choice((-1.0, 1.0), size=len(rho_s))
+    e_s = [o.eos_thermo(r, t)[1] for r, t in zip(rho_s, T_s)]
+    means = {}
+    for dex in (1e-1, 1e-2, 3e-3, 1e-4, 1e-6, 1e-8):
+        its = []
+        for r, e, t, sg in zip(rho_s, e_s, T_s, sign):
+            Tn, it, fb = o.eos_invert(r, e, t * 10.0 ** (sg * dex))
+            assert fb == 0
+            assert abs(Tn - t) <= 2e-11 * t
+            its.append(it)
+        means[dex] = float(np.mean(its))
+    print({k: round(v, 2) for k, v in means.items()})
+    vals = [means[d] for d in sorted(means, reverse=True)]
+    assert all(a >= b for a, b in zip(vals, vals[1:])), means
+    assert means[1e-8] == 1.0
+    assert means[3e-3] >= 2.0
