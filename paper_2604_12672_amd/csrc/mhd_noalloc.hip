@@ -35,13 +35,19 @@ constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 double *g_ptr[kMaxDevices] = {};
 
-// device address of this device's copy of `scratch` (resolved once per
-// device, with that device current)
+// device address of this device's copy of `scratch`, resolved once per
+// device with that device current, after checking that the device is a
+// gfx950 (hipErrorInvalidDeviceFunction if not): later calls on the device
+// only read the table
 hipError_t scratch_ptr(int dev, double **out) {
   std::lock_guard<std::mutex> lock(g_mu);
   if (!g_ptr[dev]) {
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return e;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return hipErrorInvalidDeviceFunction;
     void *p = nullptr;
-    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return e;
     g_ptr[dev] = static_cast<double *>(p);
   }
@@ -91,14 +97,11 @@ int mhd_compute_dt_noalloc(const mhd_grid_desc *desc, const double *U, const dou
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(MHD_ERR_NO_DEVICE, "no HIP device");
   if (dev < 0 || dev >= kMaxDevices) return fail(MHD_ERR_NO_DEVICE, "device index out of range");
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-      std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(MHD_ERR_NO_DEVICE, "device is not gfx950");
   double *sp = nullptr;
   hipError_t e = scratch_ptr(dev, &sp);
+  if (e == hipErrorInvalidDeviceFunction) return fail(MHD_ERR_NO_DEVICE, "device is not gfx950");
   if (e != hipSuccess)
-    return fail(MHD_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    return fail(MHD_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e));
   mhd::Phys ph{};
   mhd::fill_phys(desc, ph);
   hipStream_t s = (hipStream_t)hip_stream;
