@@ -734,6 +734,12 @@ def main():
                    "launch": r["info"], "kernel_sources": kernel_digest()},
         "roofline": roofline(w, r["stage_ms"], main_name),
         "divb_max": r["diag"]["divb_max"],
+        # the paper's own scaling, on its CPU hardware (context only: one GPU
+        # here, no scaling measured)
+        "paper_scaling_context": (
+            "weak scaling of the MPI CPU code (Sect. 2, code scaling): 64 -> 32768 "
+            "Intel Xeon Ice Lake 2.4 GHz cores on HoreKa, parallel efficiency lower by "
+            "about 24 % with 32^3 cells per core and about 15 % with 64^3 cells per core"),
     }
     ceil = stream_ceiling()
     out["roofline"]["measured_copy_GBs"] = round(ceil, 1)
