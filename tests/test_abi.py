@@ -118,3 +118,35 @@ def test_math_check_validates_before_launching(lib):
     assert lib.mhd_math_check(None, None, -1, None) == -1
     assert lib.mhd_math_check(None, None, 5, None) == -1
     assert lib.mhd_math_check(None, None, 0, None) == 0
+
+
+@pytest.mark.parametrize("shape,passes", [
+    ((1000, 1000, 4000), True),      # exactly 4e9 cells: the largest accepted count
+    ((1000, 1000, 4001), False),     # one plane more
+    ((65536, 32767, 1), True),       # nx ny (nz+1) = 2^32 - 2^17
+    ((65536, 32768, 1), False),      # nx ny (nz+1) = 2^32: linear indices would wrap
+    ((65536, 65536, 1), False),
+])
+def test_grid_size_limits(lib, shape, passes):
+    """The two size limits of the descriptor check, at their edges: linear
+    cell indices (face planes included) stay below 2^32, and the cell count
+    at or below 4e9.  A grid that passes the check fails next for want of a
+    device here (MHD_ERR_NO_DEVICE); one past a limit is an argument error.
+    Skipped where a GPU is present, where a passing grid would go on to
+    allocate hundreds of GB."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a device is present: the passing grids would be allocated")
+    except ImportError:
+        pass
+    nx, ny, nz = shape
+    d = _desc(nx=nx, ny=ny, nz=nz)
+    h = C.c_void_p()
+    rc = lib.mhd_init_grid(C.byref(d), None, C.byref(h))
+    assert not h.value
+    if passes:
+        assert rc == -2, (shape, rc, lib.mhd_last_error(None))
+    else:
+        assert rc == -1, (shape, rc)
+        assert b"too large" in lib.mhd_last_error(None)
