@@ -730,7 +730,7 @@ static void launch_stage_t(const Ctx &c, const StagePtrs &p, double a, double b,
 }
 
 // the variant the context's stages run (occupancy for the segment length;
-// a forcing field set later only changes the variant, not the result)
+// forcing modes set later only change the variant, not the result)
 template <typename R>
 static const void *stage_fn(const Ctx &c) {
   const bool xf = c.d.flatten || c.d.nspecies > 0;

@@ -1,6 +1,7 @@
 """Host-side behaviour that needs no GPU: the binding refuses to run
-without the built HIP library (there is no fallback path), and bench.py
-refuses more than one GPU."""
+without the built HIP library (there is no fallback path), bench.py
+refuses more than one GPU, prices the roofline on the algorithmic bytes,
+and keys its counter tables by the kernels' code, not their comments."""
 import os
 import subprocess
 import sys
@@ -64,3 +65,16 @@ def test_algorithmic_bytes_of_the_roofline():
     assert bench.species_bytes(ns) == pytest.approx(288.0)
     # RKL2 stage: 7 doubles read, 3 (internal-energy form) or 2 (T form) written
     assert bench.BYTES_RKL2_STAGE == {0: 7 * 8.0 + 3 * 8.0, 1: 7 * 8.0 + 2 * 8.0}
+
+
+def test_kernel_digest_follows_code_not_comments():
+    """The counter tables are keyed by a digest of the kernels' code text:
+    a comment or blank-space edit keeps it, any code edit changes it, and a
+    comment marker inside a literal is code."""
+    import bench
+    src = 'x = a / b;  // ratio\n/* block */ y = "a // b";\nz = \'/\';\n'
+    assert bench.code_text(src) == 'x = a / b; y = "a // b"; z = \'/\';'
+    assert bench.code_text(src) == bench.code_text(src.replace("ratio", "quotient").replace("  ", " "))
+    assert bench.code_text(src) != bench.code_text(src.replace("a / b", "a * b"))
+    assert bench.code_text(src) != bench.code_text(src.replace('"a // b"', '"a / b"'))
+    assert len(bench.kernel_digest()) == 16
