@@ -47,18 +47,15 @@ __device__ __forceinline__ double fraction_face(double xm, double xc, double xp,
   double h = (5.0 * xc - xm + 2.0 * xp) * (1.0 / 6.0);
   l = clamp_between(l, xm, xc);
   h = clamp_between(h, xc, xp);
-  if ((h - xc) * (xc - l) <= 0.0) {
-    l = xc;
-    h = xc;
-  } else {
-    const double d = h - l;
-    const double m6 = 6.0 * (xc - 0.5 * (l + h));
-    if (d * m6 > d * d)
-      l = 3.0 * xc - 2.0 * h;
-    else if (-d * d > d * m6)
-      h = 3.0 * xc - 2.0 * l;
-  }
-  return upper ? h : l;
+  // the three cases without branches (the lanes of a wave rarely agree)
+  const bool ext = (h - xc) * (xc - l) <= 0.0;
+  const double d = h - l;
+  const double m6 = 6.0 * (xc - 0.5 * (l + h));
+  const bool lo_over = d * m6 > d * d;
+  const bool hi_over = !lo_over && -d * d > d * m6;
+  const double lf = ext ? xc : (lo_over ? 3.0 * xc - 2.0 * h : l);
+  const double hf = ext ? xc : (hi_over ? 3.0 * xc - 2.0 * l : h);
+  return upper ? hf : lf;
 }
 
 // index of cell a along an axis of n cells: periodic, or the mirror image
