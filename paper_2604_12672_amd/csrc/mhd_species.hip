@@ -190,12 +190,10 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     double sum = 0.0;
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-      t[j] = 0.0;
-      if (l0 + j < ns) {
-        t[j] = fraction_face((up ? w[0][j] : w[1][j]) * im, (up ? w[1][j] : w[2][j]) * ic,
-                             (up ? w[2][j] : w[3][j]) * ip, up, par);
-        sum += t[j];
-      }
+      // a species past ns is zero in every slot, so its face value is zero
+      t[j] = fraction_face((up ? w[0][j] : w[1][j]) * im, (up ? w[1][j] : w[2][j]) * ic,
+                           (up ? w[2][j] : w[3][j]) * ip, up, par);
+      sum += t[j];
     }
     sum += pair_other(sum);
     const double g = F * rcp<double>(sum) * ph.idz;
@@ -213,12 +211,11 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     double sum = 0.0;
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-      v[j] = 0.0;
-      if (l0 + j < ns) {
-        const double *x = sX[l0 + j];
-        v[j] = fraction_face(x[c - stride], x[c], x[c + stride], up, par);
-        sum += v[j];
-      }
+      // rows past ns are never staged: their value is selected away
+      const double *x = sX[l0 + j];
+      const double f = fraction_face(x[c - stride], x[c], x[c + stride], up, par);
+      v[j] = l0 + j < ns ? f : 0.0;
+      sum += v[j];
     }
     sum += pair_other(sum);
     const double g = (side ? F : -F) * rcp<double>(sum) * idd;
