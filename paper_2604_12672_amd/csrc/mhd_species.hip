@@ -188,13 +188,20 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     const double im = up ? wir[0] : wir[1], ic = up ? wir[1] : wir[2],
                  ip = up ? wir[2] : wir[3];
     double sum = 0.0;
+    // one branch per face on the reconstruction (the same for all species)
+    auto faces = [&](bool parabola) {
 #pragma unroll
-    for (int j = 0; j < NH; ++j) {
-      // a species past ns is zero in every slot, so its face value is zero
-      t[j] = fraction_face((up ? w[0][j] : w[1][j]) * im, (up ? w[1][j] : w[2][j]) * ic,
-                           (up ? w[2][j] : w[3][j]) * ip, up, par);
-      sum += t[j];
-    }
+      for (int j = 0; j < NH; ++j) {
+        // a species past ns is zero in every slot, so its face value is zero
+        t[j] = fraction_face((up ? w[0][j] : w[1][j]) * im, (up ? w[1][j] : w[2][j]) * ic,
+                             (up ? w[2][j] : w[3][j]) * ip, up, parabola);
+        sum += t[j];
+      }
+    };
+    if (par)
+      faces(true);
+    else
+      faces(false);
     sum += pair_other(sum);
     const double g = F * rcp<double>(sum) * ph.idz;
 #pragma unroll
@@ -209,14 +216,21 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     const bool par = pph && !sFl[c];
     double v[NH];
     double sum = 0.0;
+    // one branch per face on the reconstruction (the same for all species)
+    auto faces = [&](bool parabola) {
 #pragma unroll
-    for (int j = 0; j < NH; ++j) {
-      // rows past ns are never staged: their value is selected away
-      const double *x = sX[l0 + j];
-      const double f = fraction_face(x[c - stride], x[c], x[c + stride], up, par);
-      v[j] = l0 + j < ns ? f : 0.0;
-      sum += v[j];
-    }
+      for (int j = 0; j < NH; ++j) {
+        // rows past ns are never staged: their value is selected away
+        const double *x = sX[l0 + j];
+        const double f = fraction_face(x[c - stride], x[c], x[c + stride], up, parabola);
+        v[j] = l0 + j < ns ? f : 0.0;
+        sum += v[j];
+      }
+    };
+    if (par)
+      faces(true);
+    else
+      faces(false);
     sum += pair_other(sum);
     const double g = (side ? F : -F) * rcp<double>(sum) * idd;
 #pragma unroll
