@@ -220,10 +220,9 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     auto faces = [&](bool parabola) {
 #pragma unroll
       for (int j = 0; j < NH; ++j) {
-        // rows past ns are never staged: their value is selected away
+        // rows past ns hold zeros: their face value is zero
         const double *x = sX[l0 + j];
-        const double f = fraction_face(x[c - stride], x[c], x[c + stride], up, parabola);
-        v[j] = l0 + j < ns ? f : 0.0;
+        v[j] = fraction_face(x[c - stride], x[c], x[c + stride], up, parabola);
         sum += v[j];
       }
     };
@@ -285,14 +284,14 @@ __global__ __launch_bounds__(256) void species_kernel(Phys ph, SpeciesPtrs p, in
     const double Fxl = fxl, Fxu = fxu, Fyl = fyl, Fyu = fyu, Fzu = fzu;
     if (k + 1 < z1) load_flux(k + 1);
     // stage plane k: the own column from the registers, one halo cell
+    // every row of the lane's species, the absent ones (zero) included, so
+    // that the face values read from them are exactly zero
 #pragma unroll
-    for (int j = 0; j < NH; ++j)
-      if (l0 + j < ns) sX[l0 + j][lpos] = w[1][j] * wir[1];
+    for (int j = 0; j < NH; ++j) sX[l0 + j][lpos] = w[1][j] * wir[1];
     if (!half) sFl[lpos] = (unsigned char)wf[1];
     if (hal) {
 #pragma unroll
-      for (int j = 0; j < NH; ++j)
-        if (l0 + j < ns) sX[l0 + j][hpos] = hx[j] * hir;
+      for (int j = 0; j < NH; ++j) sX[l0 + j][hpos] = hx[j] * hir;
       if (!half) sFl[hpos] = (unsigned char)hfl;
       if (k + 1 < z1) load_halo(k + 1);
     }
