@@ -80,14 +80,19 @@ def fields(st):
             "E": st["U"][4], "Bx": st["Bx"], "By": st["By"], "Bz": st["Bz"]}
 
 
-def momentum_floor(w, dts):
+# sum of the stage coefficients c of the residual (U = a U^n + b U^(s) - c dt R)
+RK2_WEIGHT = 1.0 + 0.5
+RK3_WEIGHT = 1.0 + 0.25 + 2.0 / 3.0
+
+
+def momentum_floor(w, dts, weight=RK2_WEIGHT):
     """Per-cell rounding floor of the oracle's momentum: ~eps P_hat per face
-    and stage (literal F - F_hat), 6 faces, stage weights 1 + 1/2."""
+    and stage (literal F - F_hat), 6 faces, summed over the stage weights."""
     if w.bg_cc is None:
         return 0.0
     p = w.params
     dxm = min((p["hi"][a] - p["lo"][a]) / (p["nx"], p["ny"], p["nz"])[a] for a in range(3))
-    return 8 * EPS * float(np.max(w.bg_cc[1])) * sum(6 * 1.5 * dt / dxm for dt in dts)
+    return 8 * EPS * float(np.max(w.bg_cc[1])) * sum(6 * weight * dt / dxm for dt in dts)
 
 
 def compare_full(out, ref):
@@ -98,8 +103,8 @@ def compare_full(out, ref):
             for k in FIELDS}
 
 
-def check_fp64(res, w, dts, what):
-    floor = momentum_floor(w, dts)
+def check_fp64(res, w, dts, what, weight=RK2_WEIGHT):
+    floor = momentum_floor(w, dts, weight)
     for name, (d, scale, l2, *_) in res.items():
         if name.startswith("m_"):
             # per-cell bound: the oracle's rounding floor dominates
@@ -112,23 +117,23 @@ def check_fp64(res, w, dts, what):
         assert l2 <= 1e-10, (what, name, l2)
 
 
-def split_floor(w, dts, st):
+def split_floor(w, dts, st, weight=RK2_WEIGHT):
     """Per-cell rounding floor of the split path's momentum.  The magnetic
     field has no background, so the magnetic pressure and tension enter the
     FP32 momentum flux at full size: each face flux carries ~eps32 (B^2/2 +
-    |B|^2) of rounding, 6 faces per cell, stage weights 1 + 1/2."""
+    |B|^2) of rounding, 6 faces per cell, summed over the stage weights."""
     p = w.params
     dxm = min((p["hi"][a] - p["lo"][a]) / (p["nx"], p["ny"], p["nz"])[a] for a in range(3))
     b2 = float(np.max(st["Bx"] ** 2) + np.max(st["By"] ** 2) + np.max(st["Bz"] ** 2))
-    return 2 * EPS32 * 1.5 * b2 * sum(6 * 1.5 * dt / dxm for dt in dts)
+    return 2 * EPS32 * 1.5 * b2 * sum(6 * weight * dt / dxm for dt in dts)
 
 
-def check_split(res, w, dts, st, what):
+def check_split(res, w, dts, st, what, weight=RK2_WEIGHT):
     """rel L2 <= 1e-5 per field.  Momentum: rel L2 <= 1e-5 or, where the
     momentum itself is at the FP32 resolution of the magnetic terms of its
     flux (a few steps into a static atmosphere, |u| ~ 1e-8 c_s), the L2 form
     of that floor."""
-    floor = split_floor(w, dts, st)
+    floor = split_floor(w, dts, st, weight)
     for name, c in res.items():
         if name.startswith("m_"):
             ok = c.l2 <= 1e-5 or c.l2 * c.l2ref <= floor * math.sqrt(c.n)
@@ -156,6 +161,29 @@ def test_stratified_256_full_oracle(mhd, precision):
         check_fp64(res, w, [dt], "256 fp64")
     else:
         check_split(res, w, [dt], ref, "256 split")
+    assert diag["divb_max"] < 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pph_rk3_stratified_256_full_oracle(mhd, precision):
+    """The paper's production scheme (PPH reconstruction, SSP-RK3 at CFL
+    0.8; Sect. 2.5, 2.9) on the 256^3 stratified box: one step against the
+    full-grid oracle, in both precisions."""
+    print(f"case pph rk3 stratified 256^3 precision={precision}", flush=True)
+    w = wl.stratified_box(256)
+    w.params = dict(w.params, recon=orc.RECON_PPH, rk_order=3)
+    w.cfl = 0.8
+    o = orc.Oracle(w.params, **w.extras())
+    ref = w.state()
+    dt = o.compute_dt(ref, w.cfl)
+    o.step(ref, dt)
+    out, diag, _ = gpu_run(mhd, w, 1, precision, dts=[dt])
+    res = compare_full(out, ref)
+    print({k: (f"{v.dmax:.2e}", f"{v.l2:.2e}") for k, v in res.items()}, flush=True)
+    if precision == 0:
+        check_fp64(res, w, [dt], "256 pph fp64", RK3_WEIGHT)
+    else:
+        check_split(res, w, [dt], ref, "256 pph split", RK3_WEIGHT)
     assert diag["divb_max"] < 1e-12
 
 
