@@ -769,7 +769,11 @@ constexpr int RED_THREADS = 256;
 constexpr int RED_BLOCKS = CFL_MAX_BLOCKS;
 
 template <bool GR, bool ML>
-__global__ __launch_bounds__(RED_THREADS) void signal_speed_kernel(
+// Three waves per SIMD at least: the variant with the learned guess would
+// otherwise take 181 registers (two waves) and wait on memory; at 168 it
+// spills five registers and runs 8 % faster (the other variants use 66).
+__global__ __launch_bounds__(RED_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void
+signal_speed_kernel(
     Phys ph, const double *__restrict__ U, const double *__restrict__ Bx,
     const double *__restrict__ By, const double *__restrict__ Bz,
     const double *__restrict__ T, const void *mlp, double *__restrict__ partial,
@@ -973,8 +977,9 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
   const int lane = threadIdx.x & 63;
   // every lane of a wave runs the matrix passes; lanes past the end repeat
   // the last cell and store nothing
-  // cell data of one cell: U and the six faces (the next cell's data is
-  // requested before this one is evaluated)
+  // cell data of one cell: U and the six faces (read at the top of each
+  // pass: without a prefetch of the next cell the kernel fits 156 registers
+  // and three waves per SIMD, which hide the latency better)
   auto fetch = [&](size_t q, double u[5], double f[6]) {
     int i, j, k;
     cell_ijk(ph, q, i, j, k);
@@ -992,20 +997,15 @@ __global__ __launch_bounds__(256) void mlp_guess_kernel(Phys ph, const double *_
   };
   const size_t stride = (size_t)gridDim.x * 256;
   size_t base = (size_t)blockIdx.x * 256;
-  double un[5] = {1, 0, 0, 0, 1}, fn[6] = {0, 0, 0, 0, 0, 0};
   unsigned long long nit = 0, nmax = 0, nfb = 0;
-  if (base < n) fetch(base + threadIdx.x < n ? base + threadIdx.x : n - 1, un, fn);
   for (; base < n; base += stride) {
     const bool valid = base + threadIdx.x < n;
     const size_t q = valid ? base + threadIdx.x : n - 1;
-    double u[5], b[3];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) u[c] = un[c];
+    double u[5], b[3], fn[6];
+    fetch(q, u, fn);
     b[0] = 0.5 * (fn[0] + fn[1]);
     b[1] = 0.5 * (fn[2] + fn[3]);
     b[2] = 0.5 * (fn[4] + fn[5]);
-    if (base + stride < n)
-      fetch(base + stride + threadIdx.x < n ? base + stride + threadIdx.x : n - 1, un, fn);
     float x0, x1;
     const double e = specific_eint(u, b);
     mlp_inputs(ph, u[0], e, x0, x1);
