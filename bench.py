@@ -59,7 +59,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "96a4ce01aaf18e08": {"fp64": (1485790.0, 1108687.9), "split": (1818705.7, 1223683.1)},
+    "0d325dd16c6a86b4": {"fp64": (1484686.6, 1106987.2), "split": (1821960.2, 1224056.0)},
 }
 
 
@@ -69,7 +69,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "96a4ce01aaf18e08": {"fp64": 911465283, "split": 624704211},
+    "0d325dd16c6a86b4": {"fp64": 911465283, "split": 624704211},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
@@ -77,7 +77,7 @@ VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 # HBM traffic of diff_stage_kernel (FETCH_SIZE, WRITE_SIZE in KiB per
 # dispatch, averaged over a super step) for the digest of its sources
 RKL2_TRAFFIC_KIB = {
-    "53f859047060231e": {"eint": (501491.7, 397803.5), "temp": (502751.0, 266731.5)},
+    "53f859047060231e": {"eint": (501489.2, 397803.5), "temp": (502686.9, 266731.5)},
 }
 
 
