@@ -237,13 +237,38 @@ __device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, i
 // XF: the optional features of a stage (forcing modes, shock-flattening
 // flags, species mass fluxes); the variant without them carries none of
 // their code, pointers or registers.
+// The arguments of one stage launch, passed as the kernel's only argument,
+// so that they start at offset 0 of the kernel-argument segment.
+struct StageArgs {
+  Phys ph;
+  StagePtrs p;
+  double ca, cb, cc, dt_host;  // U^(s+1) = cb U^(s) - cc dt L(U^(s)) + ca U^n
+  int zseg;                    // planes per z segment
+};
+
+// The stage's arguments read again from the argument segment, as a view
+// the compiler cannot hoist (the asm hides that the address is the same
+// each time).  Inside the plane loop the kernel keeps more uniform values
+// live (pointers, constants, field offsets, branch conditions) than the
+// 102 scalar registers hold; the compiler then parks the excess in lanes
+// of vector registers and pays one v_readlane per 32-bit word at every
+// use.  Taken from this view once per plane, the values are scalar loads
+// (through the scalar cache, no vector issue slot) near their use.
+__device__ __forceinline__ const StageArgs &stage_args_view() {
+  using KA = const __attribute__((address_space(4))) StageArgs;
+  KA *a = (KA *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(a));
+  return *(const StageArgs *)a;
+}
+
 template <typename R, bool GR, bool XF>
-__global__ __launch_bounds__(NTHREADS) void stage_kernel(
-    Phys ph, StagePtrs p, double ca, double cb, double cc, double dt_host,
-    int zseg) {
+__global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
+  const Phys &ph = args.ph;
+  const StagePtrs &p = args.p;
+  const double cc = args.cc, dt_host = args.dt_host;
+  const int zseg = args.zseg;
   static_assert(sizeof(MlpLds) % 16 == 0, "MlpLds is copied in 16-byte words");
   constexpr int NF = Cfg<R, GR>::NF;
-  constexpr bool EARLY = sizeof(R) == 8 || !GR;
   // FP64 runs one wave per SIMD (register-bound): it has the registers to
   // hold the next plane's cell data while it works on the current one
   constexpr bool PREFETCH = sizeof(R) == 8;
@@ -287,7 +312,6 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
   __shared__ double sZB[XF ? FZB : 1][ZSEG_MAX + 4];
   __shared__ R sFC[XF ? 3 * FZB : 1][NTHREADS];
   const size_t plane = (size_t)ph.nx * ph.ny;
-  const size_t ncell = plane * ph.nz;
   const size_t colq = (size_t)gj * ph.nx + gi;
   {
     const int nq = z1 - z0 + 4, nf = z1 - z0 + 1;
@@ -371,10 +395,18 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, k0, mir0, prc);
   }
   for (int k = z0 - 4; k < z1; ++k) {
-    // every global value P3 and P4 read, requested together: at the top of
-    // the plane so that the latency overlaps P1 and P2, except where the
-    // registers that costs would lower the occupancy (FP32 gas+radiation
-    // with the stored guess), then at the start of P3
+    // this plane's view of the arguments (shadows the kernel's own names);
+    // FP32 variants only: the FP64 kernel, one wave per SIMD and bound by
+    // latency, ran no faster with the scalar loads (the gas+radiation
+    // variant 0.7 % slower)
+    const StageArgs &A = sizeof(R) == 4 ? stage_args_view() : args;
+    const Phys &ph = A.ph;
+    const StagePtrs &p = A.p;
+    const double ca = A.ca, cb = A.cb;
+    const size_t plane = (size_t)ph.nx * ph.ny;
+    const size_t ncell = plane * ph.nz;
+    // every global value P3 and P4 read, requested together at the top of
+    // the plane so that the latency overlaps P1 and P2
     const bool upd = k >= z0 && owner;
     const bool updz = k >= z0 - 1 && k + 1 < z1 && owner && !(ph.reflect && k + 1 == 0);
     const bool base = ca != 0.0;
@@ -382,22 +414,19 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     const size_t qfz = (size_t)(k + 1 > 0 ? k + 1 : 0) * plane + colq;
     double us[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0};
     double bxs = 0.0, bys = 0.0, bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
-    auto load_update = [&]() {
-      if (upd) {
+    if (upd) {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + qc];
-        bxs = p.Bxs[qc];
-        bys = p.Bys[qc];
-        if (base) {
+      for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + qc];
+      bxs = p.Bxs[qc];
+      bys = p.Bys[qc];
+      if (base) {
 #pragma unroll
-          for (int f = 0; f < 5; ++f) u0[f] = p.U0[f * ncell + qc];
-          bx0 = p.Bx0[qc];
-          by0 = p.By0[qc];
-        }
+        for (int f = 0; f < 5; ++f) u0[f] = p.U0[f * ncell + qc];
+        bx0 = p.Bx0[qc];
+        by0 = p.By0[qc];
       }
-      if (updz && base) bz0 = p.Bz0[qfz];
-    };
-    if (EARLY) load_update();
+    }
+    if (updz && base) bz0 = p.Bz0[qfz];
     // ---------------- P1 ------------------------------------------------
     // primitives of plane k+2 (staged in LDS), z reconstruction of cell
     // k+1 and the z-face k+1/2, x/y reconstruction of cell k+1
@@ -573,7 +602,6 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(
     const R zf_m_l = from_left(zf_m);
     const R ry_l = from_left(ry);
     const R ry_prev_l = from_left(ry_prev);
-    if (!EARLY) load_update();
     R ex_new = 0, ey_new = 0, ez_new = 0;
     if (k >= z0 - 1) {
       // cells of plane k
@@ -713,11 +741,11 @@ static void launch_stage_g(const Ctx &c, const StagePtrs &p, double a, double b,
                            double dt_host, dim3 grid) {
   dim3 block(NTHREADS);
   if (p.fcoef || p.flat || p.mfx || p.mfy || p.mfz)
-    hipLaunchKernelGGL((stage_kernel<R, GR, true>), grid, block, 0, c.stream, c.ph, p, a, b, cc,
-                       dt_host, c.zseg);
+    hipLaunchKernelGGL((stage_kernel<R, GR, true>), grid, block, 0, c.stream,
+                       StageArgs{c.ph, p, a, b, cc, dt_host, c.zseg});
   else
-    hipLaunchKernelGGL((stage_kernel<R, GR, false>), grid, block, 0, c.stream, c.ph, p, a, b,
-                       cc, dt_host, c.zseg);
+    hipLaunchKernelGGL((stage_kernel<R, GR, false>), grid, block, 0, c.stream,
+                       StageArgs{c.ph, p, a, b, cc, dt_host, c.zseg});
 }
 
 template <typename R>

@@ -14,16 +14,7 @@ without asm, plus one for each asm statement in the window -- enough even
 if every asm statement had been counted as an instruction.  CPU only
 (cross-compiles; needs hipcc)."""
 import collections
-import os
 import re
-import shutil
-import subprocess
-
-import pytest
-
-from paper_2604_12672_amd import build
-
-CSRC = os.path.join(os.path.dirname(build.__file__), "csrc")
 
 
 def _vregs(tok):
@@ -70,15 +61,8 @@ def mfma_windows(lines):
     return out
 
 
-@pytest.mark.skipif(shutil.which(build.HIPCC) is None and not os.path.exists(build.HIPCC),
-                    reason="hipcc not available")
-def test_asm_statements_never_stand_for_mfma_wait_states(tmp_path):
-    flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC")]
-    out = tmp_path / "kernels.s"
-    subprocess.run([build.HIPCC] + flags + ["-I", CSRC, "--cuda-device-only", "-S",
-                    os.path.join(CSRC, "mhd_kernels.hip"), "-o", str(out)],
-                   check=True, capture_output=True)
-    wins = mfma_windows(out.read_text().split("\n"))
+def test_asm_statements_never_stand_for_mfma_wait_states(kernels_asm):
+    wins = mfma_windows(kernels_asm)
     assert len(wins) >= 20, "the guess network's MFMAs were not found"
     need = collections.defaultdict(lambda: None)
     for op, kind, ws, nasm in wins:
