@@ -59,7 +59,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "0d325dd16c6a86b4": {"fp64": (1484686.6, 1106987.2), "split": (1821960.2, 1224056.0)},
+    "9ed69352cbb5a4d6": {"fp64": (1488102.6, 1111269.8), "split": (1844084.1, 1221895.3)},
 }
 
 
@@ -69,7 +69,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "0d325dd16c6a86b4": {"fp64": 911465283, "split": 624704211},
+    "9ed69352cbb5a4d6": {"fp64": 905327447, "split": 621552643},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
