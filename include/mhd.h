@@ -90,7 +90,8 @@ extern "C" {
 typedef struct mhd_ctx mhd_ctx; /* opaque */
 
 typedef struct {
-  int32_t nx, ny, nz;     /* interior cells, each >= 1; nx ny (nz+1) < 2^32    */
+  int32_t nx, ny, nz;     /* interior cells, each >= 1; nx ny (nz+1) < 2^32,
+                             nx ny < 2^29                                      */
   double lo[3], hi[3];    /* box corners, hi > lo                              */
   int32_t bc[3];          /* bc[0] = bc[1] = MHD_BC_PERIODIC;
                              bc[2] = MHD_BC_PERIODIC or MHD_BC_REFLECT        */
@@ -293,7 +294,8 @@ int mhd_diffuse(mhd_ctx *ctx, double dt, int32_t nsts, int32_t mode,
    (on different streams or threads) race and must be serialised by the
    caller.  Any grid the descriptor check accepts fits (the reduction
    strides over cells beyond 2048 blocks of 256); larger grids
-   (nx ny (nz+1) >= 2^32) and invalid arguments return MHD_ERR_ARG, a
+   (nx ny (nz+1) >= 2^32 or nx ny >= 2^29) and invalid arguments return
+   MHD_ERR_ARG, a
    device other than gfx950 MHD_ERR_NO_DEVICE, a failed launch MHD_ERR_HIP,
    with the message in mhd_last_error(NULL).  The result is bit for bit the
    one mhd_compute_dt gives for the same state and guesses. */

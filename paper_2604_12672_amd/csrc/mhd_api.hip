@@ -53,6 +53,12 @@ int check_desc(const mhd_grid_desc *d, std::string &msg) {
     msg = "grid too large: nx ny (nz+1) must stay below 2^32 cells";
     return MHD_ERR_ARG;
   }
+  // the stage kernel addresses a column within a plane by a 32-bit byte
+  // offset: one plane of one field stays below 4 GiB
+  if ((double)d->nx * d->ny >= 536870912.0) {
+    msg = "grid too large: nx ny must stay below 2^29 cells (one plane below 4 GiB)";
+    return MHD_ERR_ARG;
+  }
   const double cells = (double)d->nx * d->ny * d->nz;
   if (cells > 4.0e9) {
     msg = "grid too large";

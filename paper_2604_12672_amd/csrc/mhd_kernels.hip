@@ -75,25 +75,65 @@ struct CellLoad {
   double tg;
 };
 
-__device__ __forceinline__ void load_cell(const Phys &ph, const StagePtrs &p,
-                                          int gi, int gip, int gj, int gjp,
+// Element access through a plane's address and a lane's column.  The plane
+// address (array + field + plane) must be the same for every lane of the
+// wave: it is held in scalar registers (the asm's "s" constraint), and the
+// column is a 32-bit byte offset (planes stay below 4 GiB, checked at
+// grid creation), so the access takes the scalar-base form of the global
+// load and store and costs the vector unit no 64-bit address arithmetic.
+// The empty asm statements keep the compiler from folding the scalar base
+// into a per-lane address; lane_off re-states a column offset in the basic
+// block of its accesses, since the compiler chooses the address form block
+// by block.
+__device__ __forceinline__ uint32_t lane_off(uint32_t o) {
+  asm("" : "+v"(o));
+  return o;
+}
+template <typename T>
+__device__ __forceinline__ T plane_ld(const T *base, uint32_t off) {
+  using G = const __attribute__((address_space(1))) char;
+  using GT = const __attribute__((address_space(1))) T;
+  G *b = (G *)base;
+  asm("" : "+s"(b));
+  return *(GT *)(b + off);
+}
+template <typename T>
+__device__ __forceinline__ void plane_st(T *base, uint32_t off, T v) {
+  using G = __attribute__((address_space(1))) char;
+  using GT = __attribute__((address_space(1))) T;
+  G *b = (G *)base;
+  asm("" : "+s"(b));
+  *(GT *)(b + off) = v;
+}
+
+// byte offsets of a lane's column and of its +x and +y neighbours in a plane
+struct ColOff {
+  uint32_t c, xp, yp;
+};
+__device__ __forceinline__ ColOff col_off(const Phys &ph, int gi, int gip, int gj, int gjp) {
+  return {(uint32_t)(((size_t)gj * ph.nx + gi) * 8), (uint32_t)(((size_t)gj * ph.nx + gip) * 8),
+          (uint32_t)(((size_t)gjp * ph.nx + gi) * 8)};
+}
+
+__device__ __forceinline__ void load_cell(const Phys &ph, const StagePtrs &p, ColOff co,
                                           int kk, int mirror, CellLoad &c) {
   const size_t plane = (size_t)ph.nx * ph.ny;
   const size_t n = plane * ph.nz;
-  const size_t q = (size_t)kk * plane + (size_t)gj * ph.nx + gi;
-#pragma unroll
-  for (int f = 0; f < 5; ++f) c.u[f] = p.Us[f * n + q];
-  c.bxl = p.Bxs[q];
-  c.byl = p.Bys[q];
-  const double bxr = p.Bxs[(size_t)kk * plane + (size_t)gj * ph.nx + gip];
-  const double byr = p.Bys[(size_t)kk * plane + (size_t)gjp * ph.nx + gi];
+  const size_t pk = (size_t)kk * plane;
   const int kp = ph.reflect ? kk + 1 : wrapi(kk + 1, ph.nz);
-  const double bzl = p.Bzs[(size_t)kk * plane + (size_t)gj * ph.nx + gi];
-  const double bzr = p.Bzs[(size_t)kp * plane + (size_t)gj * ph.nx + gi];
+  const uint32_t o = lane_off(co.c), ox = lane_off(co.xp), oy = lane_off(co.yp);
+#pragma unroll
+  for (int f = 0; f < 5; ++f) c.u[f] = plane_ld(p.Us + f * n + pk, o);
+  c.bxl = plane_ld(p.Bxs + pk, o);
+  c.byl = plane_ld(p.Bys + pk, o);
+  const double bxr = plane_ld(p.Bxs + pk, ox);
+  const double byr = plane_ld(p.Bys + pk, oy);
+  const double bzl = plane_ld(p.Bzs + pk, o);
+  const double bzr = plane_ld(p.Bzs + (size_t)kp * plane, o);
   c.b[0] = 0.5 * (c.bxl + bxr);
   c.b[1] = 0.5 * (c.byl + byr);
   c.b[2] = 0.5 * (bzl + bzr);
-  c.tg = p.Tin ? p.Tin[q] : 0.0;
+  c.tg = p.Tin ? plane_ld(p.Tin + pk, lane_off(co.c)) : 0.0;
   (void)mirror;
 }
 
@@ -355,6 +395,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
   }
   const int rgi = wrapi(X0 + rci, ph.nx), rgip = wrapi(X0 + rci + 1, ph.nx);
   const int rgj = wrapi(Y0 + rcj, ph.ny), rgjp = wrapi(Y0 + rcj + 1, ph.ny);
+  const ColOff cofs = col_off(ph, gi, gip, gj, gjp), rofs = col_off(ph, rgi, rgip, rgj, rgjp);
   const int lw_own = (cj + 2) * LW + (ci + 2);
   const int lw_ring = (rcj + 2) * LW + (rci + 2);
   const int tdn = tid >= TT ? tid - TT : tid;            // (ci, cj-1)
@@ -391,8 +432,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
   if (PREFETCH) {
     int mir0;
     const int k0 = zsource(ph, z0 - 2, mir0);
-    load_cell(ph, p, gi, gip, gj, gjp, k0, mir0, pc);
-    if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, k0, mir0, prc);
+    load_cell(ph, p, cofs, k0, mir0, pc);
+    if (ring) load_cell(ph, p, rofs, k0, mir0, prc);
   }
   for (int k = z0 - 4; k < z1; ++k) {
     // this plane's view of the arguments (shadows the kernel's own names);
@@ -410,23 +451,25 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
     const bool upd = k >= z0 && owner;
     const bool updz = k >= z0 - 1 && k + 1 < z1 && owner && !(ph.reflect && k + 1 == 0);
     const bool base = ca != 0.0;
-    const size_t qc = (size_t)(k > 0 ? k : 0) * plane + colq;
-    const size_t qfz = (size_t)(k + 1 > 0 ? k + 1 : 0) * plane + colq;
     double us[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0};
     double bxs = 0.0, bys = 0.0, bx0 = 0.0, by0 = 0.0, bz0 = 0.0;
+    const size_t pqc = (size_t)(k > 0 ? k : 0) * plane;
+    const size_t pqf = (size_t)(k + 1 > 0 ? k + 1 : 0) * plane;
     if (upd) {
+      const uint32_t o = lane_off(cofs.c);
 #pragma unroll
-      for (int f = 0; f < 5; ++f) us[f] = p.Us[f * ncell + qc];
-      bxs = p.Bxs[qc];
-      bys = p.Bys[qc];
-      if (base) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) u0[f] = p.U0[f * ncell + qc];
-        bx0 = p.Bx0[qc];
-        by0 = p.By0[qc];
-      }
+      for (int f = 0; f < 5; ++f) us[f] = plane_ld(p.Us + f * ncell + pqc, o);
+      bxs = plane_ld(p.Bxs + pqc, o);
+      bys = plane_ld(p.Bys + pqc, o);
     }
-    if (updz && base) bz0 = p.Bz0[qfz];
+    if (upd && base) {
+      const uint32_t o = lane_off(cofs.c);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) u0[f] = plane_ld(p.U0 + f * ncell + pqc, o);
+      bx0 = plane_ld(p.Bx0 + pqc, o);
+      by0 = plane_ld(p.By0 + pqc, o);
+    }
+    if (updz && base) bz0 = plane_ld(p.Bz0 + pqf, lane_off(cofs.c));
     // ---------------- P1 ------------------------------------------------
     // primitives of plane k+2 (staged in LDS), z reconstruction of cell
     // k+1 and the z-face k+1/2, x/y reconstruction of cell k+1
@@ -452,11 +495,11 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
         if (k + 1 < z1) {
           int mirn;
           const int kn = zsource(ph, q + 1, mirn);
-          load_cell(ph, p, gi, gip, gj, gjp, kn, mirn, pc);
-          if (ring) load_cell(ph, p, rgi, rgip, rgj, rgjp, kn, mirn, prc);
+          load_cell(ph, p, cofs, kn, mirn, pc);
+          if (ring) load_cell(ph, p, rofs, kn, mirn, prc);
         }
       } else {
-        load_cell(ph, p, gi, gip, gj, gjp, kk, mir, c);
+        load_cell(ph, p, cofs, kk, mir, c);
       }
       const int maxit = p.newton_cap;
       const int jq = q - (z0 - 2);
@@ -468,7 +511,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
         byf_n = (R)c.byl;
         if (GR) {
           if (owner && q >= z0 && q < z1) {
-            if (p.Tout) p.Tout[(size_t)kk * plane + colq] = o.T;
+            if (p.Tout) plane_st(p.Tout + (size_t)kk * plane, lane_off(cofs.c), o.T);
             nit += o.iters;
             nmax = o.iters > nmax ? o.iters : nmax;
             nfb += o.fallback;
@@ -477,7 +520,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
         bad |= o.bad;
       }
       if (ring) {
-        if (!PREFETCH) load_cell(ph, p, rgi, rgip, rgj, rgjp, kk, mir, rc);
+        if (!PREFETCH) load_cell(ph, p, rofs, kk, mir, rc);
         PrimOut ro;
         R Wr[NF];
         prim_cell<R, GR>(ph, rc, bgq, mir, Wr, ro, maxit);
@@ -505,7 +548,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
           bgf.p = (R)sBf[1][jf];
           bgf.ge = (R)sBf[2][jf];
           bgf.gc = (R)sBf[3][jf];
-          bzf = p.Bzs[(size_t)fzi * plane + colq];
+          bzf = plane_ld(p.Bzs + (size_t)fzi * plane, lane_off(cofs.c));
           const R bzn = (R)bzf;
           R fz[7];
           face_flux<R, GR>(XF && (fk | fc) != 0, topk, botn, bzn, bgf, gam, igm1, ph.xi_mode,
@@ -633,8 +676,12 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
         r[2] -= s2;
         r[3] -= s3;
         r[4] -= s4;
+        {
+          const uint32_t o = lane_off(cofs.c);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) p.Uo[f * ncell + qc] = cb * us[f] - cdt * r[f] + ca * u0[f];
+          for (int f = 0; f < 5; ++f)
+            plane_st(p.Uo + f * ncell + pqc, o, cb * us[f] - cdt * r[f] + ca * u0[f]);
+        }
       }
       // x/y divergence of plane k+1
       R fyc[5];
@@ -674,14 +721,15 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
                          ((double)ey_new - (double)ey_prev) * ph.idz;
       const double rby = ((double)ex_new - (double)ex_prev) * ph.idz -
                          ((double)ez_r - (double)ez_cur) * ph.idx;
-      p.Bxo[qc] = cb * bxs - cdt * rbx + ca * bx0;
-      p.Byo[qc] = cb * bys - cdt * rby + ca * by0;
+      const uint32_t o = lane_off(cofs.c);
+      plane_st(p.Bxo + pqc, o, cb * bxs - cdt * rbx + ca * bx0);
+      plane_st(p.Byo + pqc, o, cb * bys - cdt * rby + ca * by0);
     }
     if (updz) {
       const double ex_u = (double)sEX[tup];
       const double rbz = ((double)ey_r - (double)ey_new) * ph.idx -
                          (ex_u - (double)ex_new) * ph.idy;
-      p.Bzo[qfz] = cb * bzf - cdt * rbz + ca * bz0;
+      plane_st(p.Bzo + pqf, lane_off(cofs.c), cb * bzf - cdt * rbz + ca * bz0);
     }
 
     // ---------------- shift the pipeline --------------------------------

@@ -123,14 +123,16 @@ def test_math_check_validates_before_launching(lib):
 @pytest.mark.parametrize("shape,passes", [
     ((1000, 1000, 4000), True),      # exactly 4e9 cells: the largest accepted count
     ((1000, 1000, 4001), False),     # one plane more
-    ((65536, 32767, 1), True),       # nx ny (nz+1) = 2^32 - 2^17
-    ((65536, 32768, 1), False),      # nx ny (nz+1) = 2^32: linear indices would wrap
+    ((18724, 25487, 8), True),       # nx ny (nz+1) = 2^32 - 4
+    ((18724, 25488, 8), False),      # nx ny (nz+1) > 2^32: linear indices would wrap
+    ((16384, 32767, 1), True),       # nx ny = 2^29 - 2^14
+    ((16384, 32768, 1), False),      # nx ny = 2^29: a plane's byte offsets would reach 2^32
     ((65536, 65536, 1), False),
 ])
 def test_grid_size_limits(lib, shape, passes):
-    """The two size limits of the descriptor check, at their edges: linear
-    cell indices (face planes included) stay below 2^32, and the cell count
-    at or below 4e9.  A grid that passes the check fails next for want of a
+    """The three size limits of the descriptor check, at their edges: linear
+    cell indices (face planes included) stay below 2^32, a plane below 2^29
+    cells (its byte offsets below 2^32), and the cell count at or below 4e9.  A grid that passes the check fails next for want of a
     device here (MHD_ERR_NO_DEVICE); one past a limit is an argument error.
     Skipped where a GPU is present, where a passing grid would go on to
     allocate hundreds of GB."""
