@@ -59,7 +59,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "9ed69352cbb5a4d6": {"fp64": (1488102.6, 1111269.8), "split": (1844084.1, 1221895.3)},
+    "da7be8792de44cd8": {"fp64": (1345900.6, 1108471.6), "split": (1842861.2, 1221423.6)},
 }
 
 
@@ -69,7 +69,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "9ed69352cbb5a4d6": {"fp64": 905327447, "split": 621552643},
+    "da7be8792de44cd8": {"fp64": 867271663, "split": 596419671},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 
