@@ -274,15 +274,12 @@ __device__ __forceinline__ void stage_mlp(const void *src, void *dst, int tid, i
   for (int i = tid; i < (int)(sizeof(MlpLds) / 16); i += nthreads) d4[i] = s4[i];
 }
 
-// XF: the optional features of a stage (forcing modes, shock-flattening
-// flags, species mass fluxes); the variant without them carries none of
-// their code, pointers or registers.
 // The arguments of one stage launch, passed as the kernel's only argument,
 // so that they start at offset 0 of the kernel-argument segment.
 struct StageArgs {
   Phys ph;
   StagePtrs p;
-  double ca, cb, cc, dt_host;  // U^(s+1) = cb U^(s) - cc dt L(U^(s)) + ca U^n
+  double ca, cb, cc, dt_host;  // U^(s+1) = cb U^(s) + ca U^n - cc dt (div F - S)(U^(s))
   int zseg;                    // planes per z segment
 };
 
@@ -301,6 +298,9 @@ __device__ __forceinline__ const StageArgs &stage_args_view() {
   return *(const StageArgs *)a;
 }
 
+// XF: the optional features of a stage (forcing modes, shock-flattening
+// flags, species mass fluxes); the variant without them carries none of
+// their code, pointers or registers.
 template <typename R, bool GR, bool XF>
 __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
   const Phys &ph = args.ph;
