@@ -59,7 +59,7 @@ FETCH_FACTOR = 2.0
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {
     # digest: {path: (fetch KiB, write KiB) per stage dispatch}
-    "da7be8792de44cd8": {"fp64": (1345900.6, 1108471.6), "split": (1842861.2, 1221423.6)},
+    "3f5afaf1e16d1e30": {"fp64": (1363793.3, 1115010.8), "split": (1826299.1, 1218578.1)},
 }
 
 
@@ -69,7 +69,7 @@ TRAFFIC_KIB = {
 # wave64 instruction per four cycles, 2.4 GHz) they give the launch's
 # instruction-issue floor: the bound the stage kernel actually meets.
 VALU_INSTS = {
-    "da7be8792de44cd8": {"fp64": 867271663, "split": 596419671},
+    "3f5afaf1e16d1e30": {"fp64": 863571147, "split": 596439887},
 }
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4.0
 

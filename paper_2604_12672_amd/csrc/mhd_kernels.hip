@@ -16,7 +16,9 @@
 //   P3  updates the cells of plane k, accumulates the x/y flux divergence of
 //       plane k+1 and computes the Contact-CT edge EMFs E_z(k+1), E_x and
 //       E_y(k+1/2),
-//   P4  updates the faces B_x(k), B_y(k) and B_z(k+1/2).
+//   P4  updates the faces B_x(k) and B_y(k); B_z(k+1/2), which needs the
+//       E_x(k+1/2) of the row above from P3, is updated in the next plane
+//       after its first barrier (two barriers per plane, after P1 and P2).
 // Neighbour exchanges inside a 16-lane row use lane shuffles; exchanges
 // across rows use small LDS arrays.  Fluxes and EMFs on tile borders are
 // recomputed by both neighbouring blocks from identical inputs with the
@@ -312,6 +314,9 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
   // FP64 runs one wave per SIMD (register-bound): it has the registers to
   // hold the next plane's cell data while it works on the current one
   constexpr bool PREFETCH = sizeof(R) == 8;
+  // the ring cells' data too, except in the gas + radiation variant (its
+  // Newton iteration leaves the loads time to arrive; 1 % faster without)
+  constexpr bool RING_PREFETCH = PREFETCH && !GR;
   constexpr int NS = NFS_<GR>::v;
   constexpr int LW = TT + 2;  // LDS plane edge: columns -2 .. 15
   constexpr int LP = LW * LW;
@@ -416,6 +421,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
   R fzp[5] = {0, 0, 0, 0, 0};       // z-face conserved flux at k-1/2
   R ex_prev = 0, ey_prev = 0;       // own edges E_x, E_y at k-1/2
   R ez_cur = 0;                     // own edge E_z at plane k
+  double bzf_prev = 0.0, bz0_prev = 0.0;  // B_z^(s), B_z^n of the face k+1/2 of the previous plane
   R xf_ey_prev = 0, xf_m_prev = 0;  // own x-face E_y and mass flux, plane k
   R yf_ex_prev = 0, yf_m_prev = 0;  // own y-face E_x and mass flux, plane k
   R rx_prev = 0, ry_prev = 0;       // own cell reference E_x, E_y, plane k
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
     int mir0;
     const int k0 = zsource(ph, z0 - 2, mir0);
     load_cell(ph, p, cofs, k0, mir0, pc);
-    if (ring) load_cell(ph, p, rofs, k0, mir0, prc);
+    if (RING_PREFETCH && ring) load_cell(ph, p, rofs, k0, mir0, prc);
   }
   for (int k = z0 - 4; k < z1; ++k) {
     // this plane's view of the arguments (shadows the kernel's own names);
@@ -485,18 +491,18 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
       const int q = k + 2;
       int mir;
       const int kk = zsource(ph, q, mir);
-      if (XF && p.flat) fn = p.flat[(size_t)kk * plane + colq];
+      if (XF && p.flat) fn = plane_ld(p.flat + (size_t)kk * plane, lane_off(cofs.c >> 3));
       R *sWn = &sW[q & 1][0][0];
       CellLoad c, rc;
       if (PREFETCH) {
         // plane q arrived during the previous plane; request plane q+1
         c = pc;
-        rc = prc;
+        if (RING_PREFETCH) rc = prc;
         if (k + 1 < z1) {
           int mirn;
           const int kn = zsource(ph, q + 1, mirn);
           load_cell(ph, p, cofs, kn, mirn, pc);
-          if (ring) load_cell(ph, p, rofs, kn, mirn, prc);
+          if (RING_PREFETCH && ring) load_cell(ph, p, rofs, kn, mirn, prc);
         }
       } else {
         load_cell(ph, p, cofs, kk, mir, c);
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
         bad |= o.bad;
       }
       if (ring) {
-        if (!PREFETCH) load_cell(ph, p, rofs, kk, mir, rc);
+        if (!RING_PREFETCH) load_cell(ph, p, rofs, kk, mir, rc);
         PrimOut ro;
         R Wr[NF];
         prim_cell<R, GR>(ph, rc, bgq, mir, Wr, ro, maxit);
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
           // top wall), written once, by the block that owns the cell
           const int f = k + 1;
           if (XF && p.mfz && owner && ((f >= z0 && f < z1) || (ph.reflect && f == ph.nz)))
-            p.mfz[(size_t)f * plane + colq] = (double)fz[0];
+            plane_st(p.mfz + (size_t)f * plane, lane_off(cofs.c), (double)fz[0]);
           to_cons<R>(2, fz, fzc);
           zf_ey = -fz[5];  // z-face E_y = -F_z[B_x]
           zf_ex = fz[6];   // z-face E_x = +F_z[B_y]
@@ -595,6 +601,21 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
     }
     __syncthreads();
 
+    // ---------------- B_z(k-1/2), the previous plane's z-face ------------
+    // its E_x neighbour (the row above) comes from that plane's P3, visible
+    // since the barrier above; the next write of sEX follows the barrier
+    // after P2
+    {
+      const R ey_r = from_right(ey_prev);
+      const bool updz_prev = k - 1 >= z0 - 1 && k < z1 && owner && !(ph.reflect && k == 0);
+      if (updz_prev) {
+        const double ex_u = (double)sEX[tup];
+        const double rbz = ((double)ey_r - (double)ey_prev) * ph.idx -
+                           (ex_u - (double)ex_prev) * ph.idy;
+        plane_st(p.Bzo + pqc, lane_off(cofs.c), cb * bzf_prev - cdt * rbz + ca * bz0_prev);
+      }
+    }
+
     // ---------------- P2: x- and y-faces of plane k+1 --------------------
     R fx[7], fy[7];
 #pragma unroll
@@ -618,9 +639,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
       // mass fluxes for the species: the lower x and y faces of the owned
       // cells of plane k+1
       if (XF && p.mfx && owner && k + 1 >= z0 && k + 1 < z1) {
-        const size_t qf = (size_t)(k + 1) * plane + colq;
-        p.mfx[qf] = (double)fx[0];
-        p.mfy[qf] = (double)fy[0];
+        const size_t pf = (size_t)(k + 1) * plane;
+        const uint32_t o = lane_off(cofs.c);
+        plane_st(p.mfx + pf, o, (double)fx[0]);
+        plane_st(p.mfy + pf, o, (double)fy[0]);
       }
       sXE[0][tid] = -fx[5];  // x-face E_z = -F_x[B_y]
       sXE[1][tid] = fx[0];
@@ -710,11 +732,10 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
       sEZ[(k + 1) & 1][tid] = ez_new;
       sEX[tid] = ex_new;
     }
-    __syncthreads();
 
-    // ---------------- P4: faces B_x(k), B_y(k), B_z(k+1/2) --------------
+    // ---------------- P4: faces B_x(k), B_y(k) ---------------------------
+    // E_z of the row above at plane k comes from the previous plane's P3
     const R ez_r = from_right(ez_cur);
-    const R ey_r = from_right(ey_new);
     if (upd) {
       const double ez_u = (double)sEZ[k & 1][tup];
       const double rbx = (ez_u - (double)ez_cur) * ph.idy -
@@ -725,12 +746,8 @@ __global__ __launch_bounds__(NTHREADS) void stage_kernel(StageArgs args) {
       plane_st(p.Bxo + pqc, o, cb * bxs - cdt * rbx + ca * bx0);
       plane_st(p.Byo + pqc, o, cb * bys - cdt * rby + ca * by0);
     }
-    if (updz) {
-      const double ex_u = (double)sEX[tup];
-      const double rbz = ((double)ey_r - (double)ey_new) * ph.idx -
-                         (ex_u - (double)ex_new) * ph.idy;
-      plane_st(p.Bzo + pqf, lane_off(cofs.c), cb * bzf - cdt * rbz + ca * bz0);
-    }
+    bzf_prev = bzf;
+    bz0_prev = bz0;
 
     // ---------------- shift the pipeline --------------------------------
     ez_cur = ez_new;
