@@ -295,9 +295,8 @@ int mhd_diffuse(mhd_ctx *ctx, double dt, int32_t nsts, int32_t mode,
    caller.  Any grid the descriptor check accepts fits (the reduction
    strides over cells beyond 2048 blocks of 256); larger grids
    (nx ny (nz+1) >= 2^32 or nx ny >= 2^29) and invalid arguments return
-   MHD_ERR_ARG, a
-   device other than gfx950 MHD_ERR_NO_DEVICE, a failed launch MHD_ERR_HIP,
-   with the message in mhd_last_error(NULL).  The result is bit for bit the
+   MHD_ERR_ARG, a device other than gfx950 MHD_ERR_NO_DEVICE, a failed
+   launch MHD_ERR_HIP, with the message in mhd_last_error(NULL).  The result is bit for bit the
    one mhd_compute_dt gives for the same state and guesses. */
 int mhd_compute_dt_noalloc(const mhd_grid_desc *desc, const double *U, const double *Bx,
                            const double *By, const double *Bz, const double *T, double cfl,
