@@ -79,7 +79,9 @@ struct CellLoad {
 
 // Element access through a plane's address and a lane's column.  The plane
 // address (array + field + plane) must be the same for every lane of the
-// wave: it is held in scalar registers (the asm's "s" constraint), and the
+// wave: it is held in scalar registers (the asm's "s" constraint; a base
+// the compiler holds in vector registers fails the build with an illegal
+// vector-to-scalar copy instead of being narrowed to one lane), and the
 // column is a 32-bit byte offset (planes stay below 4 GiB, checked at
 // grid creation), so the access takes the scalar-base form of the global
 // load and store and costs the vector unit no 64-bit address arithmetic.
