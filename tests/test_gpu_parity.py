@@ -332,6 +332,37 @@ def test_z_segments_bitwise_invariant(mhd, zseg):
     assert diag["divb_max"] < 1e-12
 
 
+@pytest.mark.parametrize("zseg", [5, 8])
+@pytest.mark.parametrize("gasrad", [False, True])
+def test_z_segments_bitwise_invariant_split(mhd, zseg, gasrad):
+    """The split-precision variants (FP32 reconstruction, fluxes and EMFs;
+    the gas + radiation one with its Newton inversion) give the same state
+    bit for bit for any segment length (walls included in the stratified
+    box): where a segment ends changes neither the tile-border EMFs nor the
+    face B_z update that waits for the next plane's first barrier.  Both
+    match the oracle to the split tolerance."""
+    if gasrad:
+        w, nsteps = wl.smooth_box(18, 15, 12, eos=wl.EOS_GASRAD), 3
+    else:
+        w, nsteps = wl.stratified_box(20, nz=24), 5
+    out, ref, diag, _ = run_pair(mhd, w, nsteps, precision=1)
+    os.environ["MHD_ZSEG"] = str(zseg)
+    try:
+        g = mhd.Grid(w.params, precision=1)
+        assert g.launch_info()["zseg"] == zseg
+    finally:
+        os.environ.pop("MHD_ZSEG", None)
+    g.load(w)
+    for dt in oracle_dts(w, nsteps, w.cfl):
+        g.step(dt)
+    seg = g.get_state()
+    g.close()
+    for key in ("U", "Bx", "By", "Bz"):
+        assert np.array_equal(seg[key], out[key]), key
+    assert_parity(rel_errors(out, ref), 1e-5, "z segments, split")
+    assert diag["divb_max"] < 1e-12
+
+
 @pytest.mark.parametrize("opts", [dict(rk_order=3), dict(xi_mode=1), dict(xi_mode=2),
                                   dict(rk_order=3, xi_mode=1)])
 def test_scheme_options_fp64(mhd, opts):
