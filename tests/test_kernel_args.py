@@ -1,5 +1,5 @@
-"""The stage kernel's argument layout, in the gfx950 assembly of the library
-build (CPU only: cross-compiles, needs hipcc).
+"""The stage kernel's argument layout and addressing, in the gfx950 assembly
+of the library build (CPU only: cross-compiles, needs hipcc).
 
 The stage kernel takes its arguments as one struct and, inside the plane
 loop of its FP32 variants, reads them again from the kernel-argument
@@ -8,7 +8,10 @@ data if the struct is the kernel's only explicit argument and sits at
 offset 0 of the segment.  The code-object metadata states both; each
 scalar load the kernel makes through the segment pointer (or a copy of it)
 must lie inside the struct or inside one of the hidden arguments after
-it."""
+it.  Two properties of the compiled plane loop are pinned as well: every
+global load and store takes the scalar-base form (uniform plane address,
+32-bit column offset), and the FP32 variants reload no more than a few
+scalar values from vector lanes."""
 import re
 
 LOAD_WIDTH = {"": 4, "x2": 8, "x4": 16, "x8": 32, "x16": 64}
@@ -75,6 +78,35 @@ def test_stage_kernel_takes_one_struct_at_offset_zero(kernels_asm):
         for o, w in loads:
             assert any(a <= o and o + w <= a + n for a, n, _ in args), (name, o, w, args)
         assert any(o + w <= size for o, w in loads)
+
+
+def plane_loop(lines, sym):
+    """Lines of the largest loop of the kernel `sym` (the plane loop)."""
+    s = next(i for i, x in enumerate(lines) if x.startswith(sym + ":"))
+    e = next(i for i in range(s + 1, len(lines)) if lines[i].startswith(".Lfunc_end"))
+    f = lines[s:e]
+    labels = {m.group(1): i for i, x in enumerate(f) for m in [re.match(r"^(\.LBB\w+):", x)] if m}
+    best = (0, 0, 0)
+    for i, x in enumerate(f):
+        m = re.search(r"s_(?:cbranch_\w+|branch)\s+(\.LBB\w+)", x)
+        if m and m.group(1) in labels and labels[m.group(1)] < i:
+            best = max(best, (i - labels[m.group(1)], labels[m.group(1)], i))
+    return f[best[1]:best[2] + 1]
+
+
+def test_plane_loop_addressing_and_scalar_reloads(kernels_asm):
+    kern = kernel_args(kernels_asm, r"^_ZN3mhd12stage_kernelI")
+    for name in kern:
+        loop = plane_loop(kernels_asm, name)
+        mem = [x.split(None, 1) for x in loop if re.match(r"\s+global_(load|store)", x)]
+        assert len(mem) >= 40, (name, len(mem))
+        # the scalar-base form names a scalar register pair last; the
+        # vector-address form names "off"
+        vec = [m for m in mem if m[1].split(",")[-1].strip().startswith("off")]
+        assert not vec, (name, vec[:3])
+        if name.startswith("_ZN3mhd12stage_kernelIf"):
+            reloads = sum(1 for x in loop if "v_readlane_b32" in x)
+            assert reloads <= 4, (name, reloads)
 
 
 def test_metadata_and_load_scan_on_a_listing():
