@@ -228,6 +228,15 @@ def roofline(w, stage_ms, path, learned=False):
     return out
 
 
+def hbm_target(w, ms, learned=False, frac=0.6):
+    """The step against one whose stage launches move their algorithmic bytes
+    at `frac` of the HBM peak."""
+    stages = int(w.params.get("rk_order", 2))
+    t = stages * stage_bytes(w, learned) * w.ncells / (frac * HBM_PEAK_GBS * 1e9) * 1e3
+    return {"hbm_fraction": frac, "ms_per_step_at_that_fraction": round(t, 4),
+            "ms_per_step": round(ms, 4), "ratio": round(ms / t, 2)}
+
+
 def newton_stats(w, diag, stages=2):
     """Newton statistics of the last step (all its stages)."""
     return {"newton_steps_per_cell_stage": round(diag["newton_iters"] / (w.ncells * stages), 3),
@@ -817,6 +826,7 @@ def main():
                "split_learned": dict(summary(wg, gml, "gasrad_split_learned"),
                                      **newton_stats(wg, gml["diag"])),
                "speedup_split_learned_vs_fp64": round(g64["ms"] / gml["ms"], 3),
+               "split_learned_vs_60pct_hbm": hbm_target(wg, gml["ms"], learned=True),
                "learned_guess_kernel": "one MFMA guess kernel per stage (reads U and B, "
                                        "writes the guess array the stage reads)",
                "workload": "gas+radiation box 256^3, log-uniform rho in [1e-2, 1e2] and "
